@@ -1,0 +1,185 @@
+"""Seeded synthetic workloads: simulation parameters and initial particles.
+
+This module is shared by the GPU path's tests/bench and by the CPU oracle's
+tests.  It only draws inputs (positions, momenta, weights) and chooses
+parameter values; it performs none of the method's arithmetic.
+
+Code units (the paper's TRISTAN convention, Table 1 and Sec. 5.4): dt = 1,
+lengths are such that the first radial cell at the inner conductor is about
+one unit wide, c is the Courant number in length units per step.
+
+Input recipe (all seeded through numpy's Philox bit generator):
+  * positions: uniform in each cell, in grid coordinates;
+  * pairs: an electron and a positron at the same position (zero net
+    charge, so zero initial plasma field is self-consistent);
+  * momenta: isotropic Maxwell-Juttner at temperature theta_T, each
+    particle independently, by inverse transform of the tabulated CDF;
+  * weights: uniform magnitude chosen so that omega_p dt = 0.1 in the
+    densest (innermost) cell;
+  * q/m chosen so that omega_c dt = 2 at the inner conductor.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = ["grid_params", "config", "CONFIGS", "pair_plasma", "mj_momenta", "small_config"]
+
+
+def grid_params(nr: int, nth: int, r_ratio: float, courant: float = 0.5, r_kind: str = "log",
+                th_kind: str = "eqarea") -> dict:
+    """Conductor radii and light speed for an nr x nth grid spanning
+    r_out / r_in = r_ratio.  The radial unit is chosen so that the first
+    radial cell is one unit wide; c is `courant` times the smallest cell
+    edge at the inner conductor (radial, or the equatorial meridional one)."""
+    if r_kind == "log":
+        dxi = math.log(r_ratio) / nr
+        r_in = 1.0 / dxi
+        dr0 = r_in * (math.exp(dxi) - 1.0)
+    else:
+        r_in = float(nr) / (r_ratio - 1.0)
+        dr0 = 1.0
+    r_out = r_in * r_ratio
+    dth = r_in * (2.0 / nth if th_kind == "eqarea" else math.pi / nth)
+    c = courant * min(dr0, dth)
+    return dict(nr=nr, nth=nth, r_in=r_in, r_out=r_out, r_kind=r_kind, th_kind=th_kind, c=c)
+
+
+def _inner_cell_volume(p: dict) -> float:
+    """Volume of the smallest (innermost) cell: only used to size weights."""
+    if p["r_kind"] == "log":
+        r1 = p["r_in"] * (p["r_out"] / p["r_in"]) ** (1.0 / p["nr"])
+    else:
+        r1 = p["r_in"] + (p["r_out"] - p["r_in"]) / p["nr"]
+    dcos = 2.0 / p["nth"] if p["th_kind"] == "eqarea" else 1.0 - math.cos(math.pi / p["nth"])
+    return 2.0 * math.pi / 3.0 * (r1 ** 3 - p["r_in"] ** 3) * dcos
+
+
+def plasma_weight(p: dict, particles_per_cell: float, omega_p_dt: float = 0.1) -> float:
+    """|w| such that omega_p^2 = n |w| (q/m) = omega_p_dt^2 in the innermost cell."""
+    vol = _inner_cell_volume(p)
+    return omega_p_dt ** 2 * vol / (particles_per_cell * p["q_over_m"])
+
+
+def mj_momenta(rng: np.random.Generator, n: int, theta: float):
+    """Isotropic Maxwell-Juttner momenta u = gamma v / c, density
+    u^2 exp(-gamma / theta), by inverse transform of a tabulated CDF."""
+    umax = math.sqrt((1.0 + 60.0 * theta) ** 2 - 1.0)
+    grid = np.linspace(0.0, umax, 40001)
+    pdf = grid ** 2 * np.exp(-(np.sqrt(1.0 + grid ** 2) - 1.0) / theta)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (pdf[1:] + pdf[:-1]) * np.diff(grid))])
+    cdf /= cdf[-1]
+    umag = np.interp(rng.random(n), cdf, grid)
+    mu = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    st = np.sqrt(np.maximum(0.0, 1.0 - mu * mu))
+    return umag * mu, umag * st * np.cos(ph), umag * st * np.sin(ph)
+
+
+def pair_plasma(p: dict, pairs_per_cell: int, theta_T: float, weight: float, seed: int,
+                i_range=None, j_range=None, shuffle: bool = True) -> dict:
+    """Co-located electron/positron pairs, positions uniform in each cell of
+    rows i_range x columns j_range (default: the whole grid), momenta
+    Maxwell-Juttner.  Returns float64 arrays x, y, ur, ut, up, w and uint64 id."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    i0, i1 = i_range if i_range else (0, p["nr"])
+    j0, j1 = j_range if j_range else (0, p["nth"])
+    ni, nj = i1 - i0, j1 - j0
+    npair = ni * nj * pairs_per_cell
+    cell = np.repeat(np.arange(ni * nj, dtype=np.int64), pairs_per_cell)
+    if shuffle:
+        cell = rng.permutation(cell)
+    xp = (i0 + cell // nj) + rng.random(npair)
+    yp = (j0 + cell % nj) + rng.random(npair)
+    del cell
+    n = 2 * npair
+    x = np.repeat(xp, 2)
+    y = np.repeat(yp, 2)
+    del xp, yp
+    ur, ut, up = mj_momenta(rng, n, theta_T) if theta_T > 0 else (np.zeros(n), np.zeros(n), np.zeros(n))
+    w = np.tile(np.array([weight, -weight]), npair)
+    ids = np.arange(n, dtype=np.uint64)
+    return dict(x=x, y=y, ur=ur, ut=ut, up=up, w=w, id=ids)
+
+
+def _rotator(nr, nth, bg, pairs_per_cell, steps, absorb_frac=0.1, inject=1, n_filt=3, seed=0,
+             r_ratio=12.0, r_lc_over_rin=3.0, wc_dt=2.0, theta_T=0.1, q_inj_scale=1.0):
+    p = grid_params(nr, nth, r_ratio)
+    p.update(n_filt=n_filt, absorb_cells=max(10, int(round(absorb_frac * nr))), mover="vay",
+             bg_kind=bg, B0=1.0, seed=seed)
+    p["sigma_max"] = 2.0 / p["absorb_cells"]
+    p["q_over_m"] = wc_dt * p["c"] / p["B0"]
+    p["omega"] = p["c"] / (r_lc_over_rin * p["r_in"])
+    p["t_spin"] = 1.0 / p["omega"]
+    ppc = max(2 * pairs_per_cell, 16)
+    w = plasma_weight(p, ppc)
+    p.update(inject=inject, f_inj=0.5, q_inj=w * q_inj_scale)
+    return dict(params=p, pairs_per_cell=pairs_per_cell, theta_T=theta_T, weight=w, steps=steps, seed=seed)
+
+
+def config(k: int) -> dict:
+    """The five benchmark workloads (plain FP64 method, monopole rotator,
+    dipole rotator, precision stress, batched ensemble)."""
+    if k == 0:
+        p = grid_params(64, 64, 10.0)
+        p.update(n_filt=3, absorb_cells=10, sigma_max=0.2, mover="vay", bg_kind="monopole", B0=1.0,
+                 omega=0.0, t_spin=0.0, inject=0, f_inj=0.0, seed=0)
+        p["q_over_m"] = 2.0 * p["c"] / p["B0"]
+        w = plasma_weight(p, 32)
+        p["q_inj"] = w
+        return dict(name="plain_fp64_64x64", params=p, pairs_per_cell=16, theta_T=0.1, weight=w,
+                    steps=100, seed=0)
+    if k == 1:
+        d = _rotator(512, 512, "monopole", 0, 2000, q_inj_scale=1.0)
+        d["name"] = "monopole_rotator_512x512"
+        return d
+    if k == 2:
+        d = _rotator(1024, 1024, "dipole", 32, 1000)
+        d["name"] = "dipole_rotator_1024x1024_ppc64"
+        return d
+    if k == 3:
+        d = _rotator(2048, 2048, "dipole", 24, 5000)
+        d["name"] = "precision_stress_2048x2048_ppc48"
+        return d
+    if k == 4:
+        return dict(name="batched_ensemble_64_runs", runs=batched_runs(), steps=200, warmup=50)
+    raise KeyError(k)
+
+
+def batched_runs(n_runs: int = 64, seed: int = 0):
+    """Uneven rotator runs: square grids 128..512 (steps of 64), Omega in
+    [0.1, 0.5] c/R*, r in [1, 4 R_LC], 16..64 particles per cell, monopole and
+    dipole alternating; the run index is its seed."""
+    rng = np.random.Generator(np.random.Philox(seed + 12345))
+    runs = []
+    for k in range(n_runs):
+        n = int(rng.choice(np.arange(128, 513, 64)))
+        om = float(rng.uniform(0.1, 0.5))  # in c / R*
+        r_lc = 1.0 / om                   # R_LC in R*
+        ppc = int(rng.choice([16, 32, 48, 64]))
+        bg = "monopole" if k % 2 == 0 else "dipole"
+        d = _rotator(n, n, bg, ppc // 2, 0, r_ratio=4.0 * r_lc, r_lc_over_rin=r_lc, seed=k)
+        d["name"] = f"run{k}_{bg}_{n}x{n}_ppc{ppc}"
+        runs.append(d)
+    return runs
+
+
+def small_config(nr=24, nth=20, pairs_per_cell=3, bg="monopole", omega_frac=0.0, inject=0, n_filt=2,
+                 absorb_cells=4, theta_T=0.1, seed=7, r_ratio=6.0, mover="vay", r_kind="log",
+                 th_kind="eqarea", wc_dt=2.0):
+    """A small grid for oracle pins and GPU parity cases (several tiles and a
+    ragged tail for any tile shape the GPU path uses)."""
+    p = grid_params(nr, nth, r_ratio, r_kind=r_kind, th_kind=th_kind)
+    p.update(n_filt=n_filt, absorb_cells=absorb_cells, sigma_max=2.0 / max(1, absorb_cells), mover=mover,
+             bg_kind=bg, B0=1.0, seed=seed)
+    p["q_over_m"] = wc_dt * p["c"] / p["B0"]
+    p["omega"] = omega_frac * p["c"] / p["r_in"]
+    p["t_spin"] = 0.0
+    w = plasma_weight(p, max(2 * pairs_per_cell, 2))
+    p.update(inject=inject, f_inj=0.5, q_inj=w)
+    return dict(name=f"small_{nr}x{nth}", params=p, pairs_per_cell=pairs_per_cell, theta_T=theta_T, weight=w,
+                steps=10, seed=seed)
+
+
+CONFIGS = [0, 1, 2, 3, 4]
