@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Throughput of the 2.5D axisymmetric PIC step on one MI355X.
+
+One step = the whole hot path: counting sort (every sort_interval steps),
+half Faraday, gather + push + deposit, half Faraday, current filter, Ampere
+with walls and lossy layer, surface injection.  Metric: particle-steps/s
+(live particles at the start of each step, summed over the timed steps,
+over the wall time of the timed steps), inputs resident in HBM.
+
+Workload: the aligned dipole rotator on a 1024 x 1024 log-r, equal-area grid
+with 64 particles per cell (about 67M), surface injection on, FP32 particle
+state (int32 cell + FP32 offsets) -- and the plain FP64 GPU path on the same
+input beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle-step of the push+deposit kernel: the
+# particle stream read (cell 4, two offsets, three momenta, weight) and
+# written back (cell, offsets, momenta); and per cell of the grid, the six
+# field components read and three face-charge components written once per step
+PUSH_BYTES = {"fp32": (4 + 2 * 4 + 3 * 4 + 4) + (4 + 2 * 4 + 3 * 4), "fp64": (4 + 2 * 8 + 3 * 8 + 8) + (4 + 2 * 8 + 3 * 8)}
+CELL_BYTES = {"fp32": 9 * 4, "fp64": 9 * 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval):
+    from paper_1407_1810_amd.binding import Sim
+    p = cfg["params"]
+    n = len(P["x"])
+    cap = n + 16 * (1 << 20)
+    s = Sim(p, precision=precision, capacity=cap, ids=False, tile=tile, sort_interval=sort_interval)
+    t0 = time.perf_counter()
+    s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"])
+    log(f"[{precision}] loaded {n} particles in {time.perf_counter() - t0:.1f} s")
+    s.step(warmup)
+    log(f"[{precision}] warmup {warmup} steps done")
+    s.set_timing(True)
+    c0 = s.counts()
+    t0 = time.perf_counter()
+    s.step(steps)
+    t1 = time.perf_counter()
+    c1 = s.counts()
+    st = s.stage_ms()
+    s.set_timing(False)
+    psteps = c1["particle_steps"] - c0["particle_steps"]
+    wall = t1 - t0
+    res = dict(value=psteps / wall, ms_per_step=1e3 * wall / steps, particle_steps=psteps,
+               mean_live=psteps / steps, stage_ms=st, live_end=c1["live"], injected=c1["injected"],
+               deleted=c1["deleted"])
+    log(f"[{precision}] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
+        f"stages {json.dumps({k: round(v, 4) for k, v in st.items()})}")
+    s.close()
+    return res
+
+
+def cpu_baseline(cfg, P, seconds=12.0, max_threads=16):
+    """The FP64 oracle on the host cores, same workload, bounded sample:
+    the full grid with every 4th pair of the particle set, as many steps as
+    fit in about `seconds`."""
+    from oracle import oracle as O
+    O.build()
+    nthreads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    O.set_threads(nthreads)
+    import numpy as np
+    o = O.Oracle(cfg["params"])
+    npair = len(P["x"]) // 2
+    idx = np.arange(0, npair, 4)
+    take = np.empty(2 * len(idx), dtype=np.int64)
+    take[0::2] = 2 * idx
+    take[1::2] = 2 * idx + 1
+    o.add_particles(*[P[k][take] for k in ("x", "y", "ur", "ut", "up", "w")])
+    m = o.n
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds or steps >= 50:
+            break
+    v = m * steps / el
+    log(f"[cpu oracle] {m} particles x {steps} steps in {el:.1f} s on {nthreads} threads: {v:.3e} particle-steps/s")
+    return dict(value=v, unit="particle-steps/s", cores=nthreads, kind="oracle",
+                sample=f"FP64 oracle, same 1024x1024 grid and fields, every 4th pair ({m} particles), "
+                       f"{steps} steps, {nthreads} threads")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=str, default="8x8")
+    ap.add_argument("--sort-interval", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is not sharded across "
+              f"GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+    from paper_1407_1810_amd import workloads as W
+    cfg = W.config(2)
+    p = cfg["params"]
+    t0 = time.perf_counter()
+    P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
+    n = len(P["x"])
+    log(f"generated {n} particles for {cfg['name']} in {time.perf_counter() - t0:.1f} s")
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, args.sort_interval)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, args.sort_interval)
+    cells = p["nr"] * p["nth"]
+    push_ms = r32["stage_ms"]["push"]
+    bytes_launch = PUSH_BYTES["fp32"] * r32["mean_live"] + CELL_BYTES["fp32"] * cells
+    achieved = bytes_launch / (push_ms * 1e-3) / 1e9
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, P)
+    out = {
+        "metric": "particle-steps/sec (push+deposit+field), FP32 and batched vs FP64 GPU",
+        "value": r32["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": f"{p['nr']}x{p['nth']}", "particles": n,
+                   "particles_per_cell": 2 * cfg["pairs_per_cell"], "background": p["bg_kind"],
+                   "injection": bool(p["inject"]), "n_filt": p["n_filt"], "absorb_cells": p["absorb_cells"],
+                   "tile": args.tile, "sort_interval": args.sort_interval, "precision": "fp32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push<float,4>",
+                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_launch},
+        "stage_ms": {k: round(v, 5) for k, v in r32["stage_ms"].items()},
+        "fp64_gpu": None if r64 is None else {
+            "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
+            "stage_ms": {k: round(v, 5) for k, v in r64["stage_ms"].items()},
+            "fp32_speedup": r32["value"] / r64["value"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

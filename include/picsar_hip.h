@@ -1,0 +1,178 @@
+/*
+ * picsar_hip.h -- C ABI of the MI355X (gfx950) 2.5D axisymmetric PIC step.
+ *
+ * The library advances the particle-in-cell step of Belyaev, "PICsar"
+ * (arXiv 1407.1810) on one GPU: the Yee/FDTD field update in integral form
+ * on the body-fitted (r, theta) mesh (App. A), the relativistic Vay or Boris
+ * push with field gather (Sec. 3.3), the charge-conserving Villasenor-Buneman
+ * deposit (Sec. 2, Sec. 3.3), the 1-2-1 current filter with its polar remap
+ * (App. B), conducting walls and the lossy absorbing layer (Sec. 3.4), the
+ * analytic initial fields with spin-up (Sec. 5.2) and surface pair injection
+ * (Sec. 5.3).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns a pic_status and never throws; pic_last_error()
+ *    holds the message of the last failure of a context.
+ *  - All pointers in these signatures are HOST pointers owned by the
+ *    caller; the library copies from / into them.  All device memory is
+ *    owned by the context and freed by pic_destroy().
+ *  - Units: Lorentz-Heaviside, time step dt = 1, lengths in code units, c in
+ *    length units per step.  Momenta u = gamma v / c in the local
+ *    (r, theta, phi) basis.  Particle weights w are signed macro charges.
+ *  - Grid: nr x nth cells; radial nodes i = 0..nr (conductors at 0 and nr),
+ *    meridional nodes j = 0..nth (poles at 0 and nth).  Fields follow the
+ *    staggering of eq. (offseteq), Sec. 3.1.  Field arrays exchanged through
+ *    the ABI are row-major [i][j] (j fastest) with these extents:
+ *       PIC_ER  (i+1/2, j)      nr     x (nth+1)
+ *       PIC_ETH (i, j+1/2)      (nr+1) x nth
+ *       PIC_EPH (i, j)          (nr+1) x (nth+1)
+ *       PIC_BR  (i, j+1/2)      (nr+1) x nth
+ *       PIC_BTH (i+1/2, j)      nr     x (nth+1)
+ *       PIC_BPH (i+1/2, j+1/2)  nr     x nth
+ *       PIC_FR, PIC_FTH, PIC_FPH: the face charges deposited in the last step
+ *       (charge crossing each dual face during the step, after filtering),
+ *       shaped like ER, ETH, EPH with g = 2*n_filt + 3 extra ghost rows on
+ *       each radial side (first row is i = -g).
+ *    pic_field_shape() returns the extents.
+ *  - Particles cross the ABI as FP64 absolute grid coordinates (x radial in
+ *    [-(n_filt+1), nr+n_filt+1], y meridional in [0, nth]).  Inside, a
+ *    particle is an int32 cell plus an in-cell offset of the context's
+ *    precision: an FP32 context rounds the offset (x - floor(x)), the
+ *    momenta and the weight to FP32 once, on the way in.
+ *  - pic_step() enqueues on the context's stream and synchronises before it
+ *    returns, so that device-side errors (CFL, capacity) are reported by
+ *    the call that caused them.
+ */
+#ifndef PICSAR_HIP_H
+#define PICSAR_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,     /* bad argument or descriptor */
+    PIC_ENOMEM = -2,     /* device allocation failed */
+    PIC_ECFL = -3,       /* a particle moved one cell or more in a step */
+    PIC_ECAPACITY = -4,  /* particle store full (inject or injection) */
+    PIC_ENAN = -5,       /* non-finite value found by a diagnostic */
+    PIC_EDEVICE = -6,    /* HIP runtime error */
+    PIC_ESTATE = -7      /* call out of order (e.g. step before init) */
+} pic_status;
+
+enum { PIC_R_LOG = 0, PIC_R_LIN = 1 };            /* Sec. 3.2: xi = r0 ln(r/r0) or r */
+enum { PIC_TH_EQAREA = 0, PIC_TH_LIN = 1 };       /* Sec. 3.2: theta_A = -cos(theta) or theta */
+enum { PIC_FP64 = 0, PIC_FP32 = 1 };
+enum { PIC_VAY = 0, PIC_BORIS = 1 };              /* Sec. 3.3 */
+enum { PIC_BG_NONE = 0, PIC_BG_UNIFORM_BZ = 1, PIC_BG_MONOPOLE = 2, PIC_BG_DIPOLE = 3,
+       PIC_BG_DIPOLE_COROT = 4 };
+enum { PIC_ER = 0, PIC_ETH = 1, PIC_EPH = 2, PIC_BR = 3, PIC_BTH = 4, PIC_BPH = 5,
+       PIC_FR = 6, PIC_FTH = 7, PIC_FPH = 8 };
+enum { PIC_FLAG_IDS = 1 };                        /* carry a uint64 id per particle */
+
+/* Grid, numerics and storage.  tile_r, tile_th and sort_interval choose the
+ * counting-sort tile and how often particles are re-sorted (0 = default);
+ * they change speed, never results beyond float reordering. */
+typedef struct {
+    int32_t nr, nth;          /* cells; nth >= 4 */
+    double r_in, r_out;       /* conductor radii, 0 < r_in < r_out */
+    int32_t r_kind, th_kind;  /* PIC_R_*, PIC_TH_* */
+    double c;                 /* light speed, length units per step */
+    int32_t n_filt;           /* 1-2-1 filter passes, 0..8 (App. B) */
+    int32_t absorb_cells;     /* lossy layer width in cells, 0 = off (Sec. 3.4.1) */
+    double sigma_max;         /* sigma* at the outer conductor, eq. (EBcond) */
+    int32_t precision;        /* PIC_FP64 | PIC_FP32 */
+    int32_t mover;            /* PIC_VAY | PIC_BORIS */
+    int64_t particle_capacity;/* maximum particles held at once */
+    int32_t tile_r, tile_th;  /* sort tile in cells (0 = 8 x 8) */
+    int32_t sort_interval;    /* steps between sorts (0 = 4; < 0 = never) */
+    int32_t flags;            /* PIC_FLAG_* */
+} pic_grid_desc;
+
+/* Analytic initial fields and injection (Sec. 5.2, 5.3, 4.3). */
+typedef struct {
+    int32_t bg_kind;          /* PIC_BG_* */
+    double B0;                /* field at r_in (monopole, dipole) or uniform B_z */
+    double omega;             /* final angular velocity of the inner conductor */
+    double t_spin;            /* linear spin-up time (0 = none) */
+    double q_over_m;          /* |q/m| of all macro-particles */
+    double f_inj;             /* fraction of the surface charge released per step */
+    double q_inj;             /* |charge| of one injected macro-particle */
+    int32_t inject;           /* 1: surface injection on (monopole / dipole only) */
+    uint64_t seed;            /* key of the Philox4x64-10 injection stream */
+} pic_phys_desc;
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * enqueue on (for example the caller's current stream) or NULL, in which
+ * case the context creates and owns a stream of default priority. */
+pic_status pic_create(pic_ctx **out, int device, void *hip_stream);
+
+/* Allocate and initialise the grid (fields zero), the particle store and
+ * the metric tables (computed in FP64 on the host).  Once per context. */
+pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys);
+
+/* Append n particles (host FP64 arrays of length n; id may be NULL, then
+ * ids are 0,1,2,... in order of arrival).  PIC_EINVAL if a position lies
+ * outside the ranges above, PIC_ECAPACITY if the store would overflow. */
+pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const double *y,
+                                const double *ur, const double *ut, const double *up,
+                                const double *w, const uint64_t *id);
+
+/* Advance n_steps steps: half Faraday, gather + push + deposit, half
+ * Faraday, filter, Ampere with the conducting walls and the polar caps of
+ * eq. (erpolarupdate), lossy layer, surface injection; particles are
+ * re-sorted every sort_interval steps. */
+pic_status pic_step(pic_ctx *ctx, int32_t n_steps);
+
+/* Field component comp (PIC_*) converted to FP64 into host[cap]. */
+pic_status pic_field_shape(pic_ctx *ctx, int32_t comp, int32_t *rows, int32_t *cols, int32_t *row0);
+pic_status pic_get_field(pic_ctx *ctx, int32_t comp, double *host, int64_t cap);
+/* Overwrite one E or B component from host FP64 data (rows x cols). */
+pic_status pic_set_field(pic_ctx *ctx, int32_t comp, const double *host, int64_t n);
+
+/* Live particles in storage order, FP64 absolute grid coordinates.  Any
+ * output pointer may be NULL.  *n_out receives the count; PIC_EINVAL if cap
+ * is smaller (nothing is written then). */
+pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, double *ut, double *up,
+                             double *w, uint64_t *id, int64_t cap, int64_t *n_out);
+
+/* Moments and diagnostics:
+ *  PIC_MOM_COUNTS: out[0..4] = live particles, injected total, deleted
+ *                  total, step index, particle-steps advanced since init
+ *  PIC_MOM_GAUSS:  Gauss diagnostic in FP64 (Sec. 2, App. B): out[0..N) =
+ *                  closed-surface flux of E out of each dual cell,
+ *                  out[N..2N) = the n_filt-filtered bilinear particle
+ *                  charge of that node, N = (nr+1)*(nth+1) row-major;
+ *                  rows 0 and nr of the flux are zero (surface nodes)
+ *  PIC_MOM_CARRY:  fractional injection count per theta node (nth+1)
+ *  PIC_MOM_STAGE_MS: mean device time per step, in ms, of each stage over
+ *                  the steps of the last pic_step call (out[0..8] = sort,
+ *                  first faraday, push, filter, ampere, absorb, inject,
+ *                  zeroing, whole step), from HIP events recorded on the
+ *                  context stream -- only when timing is on */
+enum { PIC_MOM_COUNTS = 0, PIC_MOM_GAUSS = 1, PIC_MOM_CARRY = 2, PIC_MOM_STAGE_MS = 3 };
+pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap);
+
+/* Set the step index (time t = index * dt) and the injection carry, so a
+ * run can be resumed from a saved state. */
+pic_status pic_set_step_index(pic_ctx *ctx, int64_t step);
+pic_status pic_set_carry(pic_ctx *ctx, const double *carry, int64_t n);
+
+/* Turn per-stage device timing (HIP events on the context stream) on/off. */
+pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
+
+/* Message of the last failed call on ctx (empty if none). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+/* Release every resource of the context. */
+void pic_destroy(pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

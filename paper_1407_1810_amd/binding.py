@@ -1,0 +1,231 @@
+"""ctypes binding of libpicsar_hip.so (the C ABI in include/picsar_hip.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+the library.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libpicsar_hip.so")
+
+R_KIND = {"log": 0, "lin": 1}
+TH_KIND = {"eqarea": 0, "lin": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+MOVER = {"vay": 0, "boris": 1}
+BG_KIND = {"none": 0, "uniform_bz": 1, "monopole": 2, "dipole": 3, "dipole_corot": 4}
+COMPS = ["Er", "Eth", "Eph", "Br", "Bth", "Bph", "Fr", "Fth", "Fph"]
+FLAG_IDS = 1
+MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS = 0, 1, 2, 3
+STAGES = ["sort", "faraday", "push", "filter", "ampere", "absorb", "inject", "zero", "total"]
+
+STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "PIC_ECAPACITY",
+          -5: "PIC_ENAN", -6: "PIC_EDEVICE", -7: "PIC_ESTATE"}
+
+EXPORTED = ["pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
+            "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
+            "pic_set_timing", "pic_last_error", "pic_destroy"]
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nth", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("r_kind", C.c_int32), ("th_kind", C.c_int32), ("c", C.c_double), ("n_filt", C.c_int32),
+                ("absorb_cells", C.c_int32), ("sigma_max", C.c_double), ("precision", C.c_int32),
+                ("mover", C.c_int32), ("particle_capacity", C.c_int64), ("tile_r", C.c_int32),
+                ("tile_th", C.c_int32), ("sort_interval", C.c_int32), ("flags", C.c_int32)]
+
+
+class PhysDesc(C.Structure):
+    _fields_ = [("bg_kind", C.c_int32), ("B0", C.c_double), ("omega", C.c_double), ("t_spin", C.c_double),
+                ("q_over_m", C.c_double), ("f_inj", C.c_double), ("q_inj", C.c_double), ("inject", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is not built; run paper_1407_1810_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB)
+        P, d, i32, i64, u64, vp = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
+        L.pic_create.argtypes = [P(vp), C.c_int, vp]
+        L.pic_init.argtypes = [vp, P(GridDesc), P(PhysDesc)]
+        L.pic_inject_particles.argtypes = [vp, i64] + [P(d)] * 6 + [P(u64)]
+        L.pic_step.argtypes = [vp, i32]
+        L.pic_field_shape.argtypes = [vp, i32, P(i32), P(i32), P(i32)]
+        L.pic_get_field.argtypes = [vp, i32, P(d), i64]
+        L.pic_set_field.argtypes = [vp, i32, P(d), i64]
+        L.pic_get_particles.argtypes = [vp] + [P(d)] * 6 + [P(u64), i64, P(i64)]
+        L.pic_get_moments.argtypes = [vp, i32, P(d), i64]
+        L.pic_set_step_index.argtypes = [vp, i64]
+        L.pic_set_carry.argtypes = [vp, P(d), i64]
+        L.pic_set_timing.argtypes = [vp, i32]
+        L.pic_last_error.argtypes = [vp]
+        L.pic_last_error.restype = C.c_char_p
+        L.pic_destroy.argtypes = [vp]
+        for name in ("pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape",
+                     "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_moments",
+                     "pic_set_step_index", "pic_set_carry", "pic_set_timing"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _up(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+class Sim:
+    """One GPU simulation.  `params` is a workload parameter dict (grid,
+    numerics and analytic-field keys, see workloads.py)."""
+
+    def __init__(self, params: dict, precision: str = "fp64", capacity: int = 1 << 20, device: int = 0,
+                 tile=(0, 0), sort_interval: int = 0, ids: bool = True, stream=None):
+        L = lib()
+        self._h = C.c_void_p()
+        rc = L.pic_create(C.byref(self._h), int(device), stream)
+        if rc != 0:
+            raise PicError(rc, "pic_create failed (no HIP device?)")
+        g = GridDesc()
+        g.nr, g.nth = int(params["nr"]), int(params["nth"])
+        g.r_in, g.r_out = float(params["r_in"]), float(params["r_out"])
+        g.r_kind = R_KIND[params.get("r_kind", "log")]
+        g.th_kind = TH_KIND[params.get("th_kind", "eqarea")]
+        g.c = float(params["c"])
+        g.n_filt = int(params.get("n_filt", 0))
+        g.absorb_cells = int(params.get("absorb_cells", 0))
+        g.sigma_max = float(params.get("sigma_max", 2.0 / max(1, g.absorb_cells)))
+        g.precision = PRECISION[precision]
+        g.mover = MOVER[params.get("mover", "vay")]
+        g.particle_capacity = int(capacity)
+        g.tile_r, g.tile_th = int(tile[0]), int(tile[1])
+        g.sort_interval = int(sort_interval)
+        g.flags = FLAG_IDS if ids else 0
+        ph = PhysDesc()
+        ph.bg_kind = BG_KIND[params.get("bg_kind", "none")]
+        ph.B0 = float(params.get("B0", 0.0))
+        ph.omega = float(params.get("omega", 0.0))
+        ph.t_spin = float(params.get("t_spin", 0.0))
+        ph.q_over_m = float(params.get("q_over_m", 1.0))
+        ph.f_inj = float(params.get("f_inj", 0.0))
+        ph.q_inj = float(params.get("q_inj", 1.0))
+        ph.inject = int(params.get("inject", 0))
+        ph.seed = int(params.get("seed", 0))
+        self.grid, self.phys = g, ph
+        self.nr, self.nth = g.nr, g.nth
+        self.precision = precision
+        self._check(L.pic_init(self._h, C.byref(g), C.byref(ph)))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PicError(rc, lib().pic_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pic_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # particles --------------------------------------------------------------
+    def add_particles(self, x, y, ur, ut, up, w, ids=None):
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, ur, ut, up, w)]
+        idp = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint64)
+        self._check(lib().pic_inject_particles(self._h, len(a[0]), *[_dp(v) for v in a], _up(idp)))
+
+    def particles(self):
+        n = int(self.counts()["live"])
+        out = {k: np.zeros(n) for k in ("x", "y", "ur", "ut", "up", "w")}
+        ids = np.zeros(n, dtype=np.uint64)
+        got = C.c_int64()
+        self._check(lib().pic_get_particles(self._h, *[_dp(out[k]) for k in ("x", "y", "ur", "ut", "up", "w")],
+                                            _up(ids), n, C.byref(got)))
+        out["id"] = ids
+        return out
+
+    # stepping ----------------------------------------------------------------
+    def step(self, n=1):
+        self._check(lib().pic_step(self._h, int(n)))
+
+    def set_step_index(self, n):
+        self._check(lib().pic_set_step_index(self._h, int(n)))
+
+    def set_timing(self, on=True):
+        self._check(lib().pic_set_timing(self._h, 1 if on else 0))
+
+    # fields ------------------------------------------------------------------
+    def shape(self, comp):
+        c = COMPS.index(comp) if isinstance(comp, str) else int(comp)
+        r, k, r0 = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().pic_field_shape(self._h, c, C.byref(r), C.byref(k), C.byref(r0)))
+        return r.value, k.value, r0.value
+
+    def get_field(self, comp):
+        c = COMPS.index(comp) if isinstance(comp, str) else int(comp)
+        r, k, _ = self.shape(c)
+        out = np.zeros((r, k))
+        self._check(lib().pic_get_field(self._h, c, _dp(out), out.size))
+        return out
+
+    def set_field(self, comp, data):
+        c = COMPS.index(comp) if isinstance(comp, str) else int(comp)
+        a = np.ascontiguousarray(data, dtype=np.float64)
+        self._check(lib().pic_set_field(self._h, c, _dp(a), a.size))
+
+    # moments -----------------------------------------------------------------
+    def counts(self):
+        out = np.zeros(5)
+        self._check(lib().pic_get_moments(self._h, MOM_COUNTS, _dp(out), 5))
+        return dict(live=int(out[0]), injected=int(out[1]), deleted=int(out[2]), step=int(out[3]),
+                    particle_steps=int(out[4]))
+
+    def gauss(self):
+        N = (self.nr + 1) * (self.nth + 1)
+        out = np.zeros(2 * N)
+        self._check(lib().pic_get_moments(self._h, MOM_GAUSS, _dp(out), out.size))
+        return out[:N].reshape(self.nr + 1, self.nth + 1), out[N:].reshape(self.nr + 1, self.nth + 1)
+
+    def carry(self):
+        out = np.zeros(self.nth + 1)
+        self._check(lib().pic_get_moments(self._h, MOM_CARRY, _dp(out), out.size))
+        return out
+
+    def set_carry(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self._check(lib().pic_set_carry(self._h, _dp(a), a.size))
+
+    def stage_ms(self):
+        out = np.zeros(9)
+        self._check(lib().pic_get_moments(self._h, MOM_STAGE_MS, _dp(out), 9))
+        return dict(zip(STAGES, out.tolist()))
+
+
+def gpu_available() -> bool:
+    """True if a HIP device is visible (used to skip GPU tests on CPU hosts)."""
+    try:
+        import torch
+        return bool(torch.cuda.is_available())
+    except Exception:
+        return False

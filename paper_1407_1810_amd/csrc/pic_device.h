@@ -1,0 +1,153 @@
+// pic_device.h -- device-side building blocks of the gfx950 PIC step.
+//
+// Everything here is templated on the storage/compute type T (float or
+// double).  Particles are an int32 cell (packed radial and meridional index)
+// plus an in-cell offset in [0, 1); the push works with local increments so
+// that an FP32 offset keeps ~1e-7 cell resolution at any radius.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kCellOff = 0x4000;            // radial index bias inside a packed cell
+constexpr uint32_t kDead = 0xFFFFFFFFu;     // packed cell of a deleted particle
+constexpr double kPi = 3.14159265358979323846;
+
+__host__ __device__ inline uint32_t pack_cell(int i, int j)
+{
+    return ((uint32_t)(i + kCellOff) << 16) | (uint32_t)j;
+}
+__host__ __device__ inline int cell_i(uint32_t c) { return (int)(c >> 16) - kCellOff; }
+__host__ __device__ inline int cell_j(uint32_t c) { return (int)(c & 0xFFFFu); }
+
+// Field storage: every component (E_r, E_th, E_ph, B_r, B_th, B_ph and the
+// face charges F_r, F_th, F_ph) uses one padded layout, element (i, j) at
+// (i + G) * pitch + j, rows i = -G .. nr + G, columns j = 0 .. nth.  Ghost
+// rows of E and B stay zero: the plasma field vanishes in the conductors.
+struct Layout {
+    int nr, nth, G, pitch;
+    __host__ __device__ int rows() const { return nr + 1 + 2 * G; }
+    __host__ __device__ size_t at(int i, int j) const { return (size_t)(i + G) * pitch + j; }
+    __host__ __device__ size_t size() const { return (size_t)rows() * pitch; }
+};
+
+enum : int { cER = 0, cETH = 1, cEPH = 2, cBR = 3, cBTH = 4, cBPH = 5, cFR = 6, cFTH = 7, cFPH = 8 };
+
+template <typename T>
+struct Fields {
+    T *c[9];
+};
+
+// Analytic initial ("vacuum") field of the rotating conductor, Sec. 5.2 and
+// Sec. 4.3; local (r, theta, phi) components at radius r, cos/sin theta.
+struct Background {
+    int kind;          // PIC_BG_*
+    double B0, r0;     // surface field and conductor radius
+};
+
+template <typename T>
+__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T k, T s, T E[3],
+                                      T B[3])
+{
+    const T B0 = (T)bg.B0, r0 = (T)bg.r0;
+    switch (bg.kind) {
+    case 1: // uniform B along the axis
+        B[0] += B0 * k;
+        B[1] -= B0 * s;
+        break;
+    case 2: { // monopole: inside corotation, outside the vacuum l = 1 field
+        const T q = r0 / r;
+        B[0] += B0 * q * q;
+        if (inside) {
+            E[1] -= B0 * r0 * q * s * inv_rl;
+        } else {
+            const T a = B0 * r0 * q * q * q * inv_rl;
+            E[0] -= (T)2 * a * k;
+            E[1] -= a * s;
+        }
+        break;
+    }
+    case 3:
+    case 4: { // dipole; corotation inside (or everywhere for the drift test), l = 2 vacuum outside
+        const T q = r0 / r;
+        const T q3 = q * q * q;
+        B[0] += (T)2 * B0 * q3 * k;
+        B[1] += B0 * q3 * s;
+        if (inside || bg.kind == 4) {
+            const T a = B0 * r0 * q * q * inv_rl;
+            E[0] += a * s * s;
+            E[1] -= (T)2 * a * s * k;
+        } else {
+            const T a = (T)2 * B0 * r0 * q3 * q * inv_rl;
+            E[0] -= a * (T)0.5 * ((T)3 * k * k - (T)1);
+            E[1] -= a * s * k;
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------
+// Movers (Cartesian).  u = gamma v / c, eps = q dt / (2 m c).
+// ---------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void vay_push(T u[3], const T E[3], const T B[3], T eps)
+{
+    const T ig = (T)1 / sqrt((T)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const T vx = u[0] * ig, vy = u[1] * ig, vz = u[2] * ig;
+    // half electric kick twice and the magnetic rotation with the old velocity
+    const T px = u[0] + (T)2 * eps * E[0] + eps * (vy * B[2] - vz * B[1]);
+    const T py = u[1] + (T)2 * eps * E[1] + eps * (vz * B[0] - vx * B[2]);
+    const T pz = u[2] + (T)2 * eps * E[2] + eps * (vx * B[1] - vy * B[0]);
+    const T tx = eps * B[0], ty = eps * B[1], tz = eps * B[2];
+    const T tau2 = tx * tx + ty * ty + tz * tz;
+    const T us = px * tx + py * ty + pz * tz;
+    const T sg = (T)1 + px * px + py * py + pz * pz - tau2;
+    const T g2 = (T)0.5 * (sg + sqrt(sg * sg + (T)4 * (tau2 + us * us)));
+    const T ign = (T)1 / sqrt(g2);
+    const T ax = tx * ign, ay = ty * ign, az = tz * ign;
+    const T sf = (T)1 / ((T)1 + ax * ax + ay * ay + az * az);
+    const T pt = px * ax + py * ay + pz * az;
+    u[0] = sf * (px + pt * ax + (py * az - pz * ay));
+    u[1] = sf * (py + pt * ay + (pz * ax - px * az));
+    u[2] = sf * (pz + pt * az + (px * ay - py * ax));
+}
+
+template <typename T>
+__device__ inline void boris_push(T u[3], const T E[3], const T B[3], T eps)
+{
+    const T mx = u[0] + eps * E[0], my = u[1] + eps * E[1], mz = u[2] + eps * E[2];
+    const T ig = (T)1 / sqrt((T)1 + mx * mx + my * my + mz * mz);
+    const T tx = eps * B[0] * ig, ty = eps * B[1] * ig, tz = eps * B[2] * ig;
+    const T f = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
+    const T qx = mx + (my * tz - mz * ty), qy = my + (mz * tx - mx * tz), qz = mz + (mx * ty - my * tx);
+    u[0] = mx + f * (qy * tz - qz * ty) + eps * E[0];
+    u[1] = my + f * (qz * tx - qx * tz) + eps * E[1];
+    u[2] = mz + f * (qx * ty - qy * tx) + eps * E[2];
+}
+
+// ---------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), used for the
+// positions of injected pairs.
+// ---------------------------------------------------------------------
+__device__ inline void philox4x64(uint64_t x[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint64_t lo0 = M0 * x[0], hi0 = __umul64hi(M0, x[0]);
+        const uint64_t lo1 = M1 * x[2], hi1 = __umul64hi(M1, x[2]);
+        const uint64_t n0 = hi1 ^ x[1] ^ k0, n2 = hi0 ^ x[3] ^ k1;
+        x[0] = n0;
+        x[1] = lo1;
+        x[2] = n2;
+        x[3] = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+}
+
+} // namespace pic

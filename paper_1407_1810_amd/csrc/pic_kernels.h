@@ -1,0 +1,845 @@
+// pic_kernels.h -- HIP kernels of the gfx950 PIC step.
+//
+//  k_faraday ...... half Faraday update of B (App. A, eq. (discreteeq))
+//  k_ampere ....... Ampere update of E with the filtered face charges, polar
+//                   caps (eq. (erpolarupdate)), walls, lossy layer on E
+//  k_absorb_b ..... lossy layer on B (eq. (EBcond)), layer rows only
+//  k_filter ....... one 1-2-1 pass with the polar remap (App. B)
+//  k_push ......... gather + Vay/Boris push + move + VB deposit, one
+//                   work-group per chunk of cell-sorted particles, fields and
+//                   face charges staged in LDS for the chunk's bounding box
+//  k_inject ....... surface pair injection (Sec. 5.3, eq. (volinjeq))
+//  k_sort_* ....... counting sort of particles by tile (serpentine order)
+//  k_node_charge,
+//  k_gauss_flux ... FP64 Gauss diagnostic
+#pragma once
+#include <climits>
+
+#include "pic_device.h"
+
+namespace pic {
+
+// Per-run metric tables, FP64 on the host, stored as T on the device.
+// Row tables are indexed by the radial node / half index, column tables by
+// the meridional one; see Engine::build_tables for their definitions.
+template <typename T>
+struct Metric {
+    const T *r_node;  // r(i), i = -G..nr+G at [i + G]
+    const T *rb;      // r(i + 1/2), i = -G..nr+G at [i + G]
+    const T *invr;    // 1 / r_i
+    const T *idr2;    // 2 / (r_{i+1}^2 - r_i^2)
+    const T *dr;      // r_{i+1} - r_i
+    const T *invrb;   // 1 / rbar_i
+    const T *invA;    // 1 / (2 pi rbar_i^2)
+    const T *idrb2;   // 2 / (rbar_i^2 - rbar_{i-1}^2)
+    const T *drb;     // rbar_i - rbar_{i-1}
+    const T *s;       // sin theta_j
+    const T *k;       // cos theta_j
+    const T *sb;      // sin thetabar_j
+    const T *icBr;    // 1 / (cos theta_j - cos theta_{j+1})
+    const T *idth;    // 1 / (theta_{j+1} - theta_j)
+    const T *idkb;    // 1 / (cos thetabar_{j-1} - cos thetabar_j), caps at the poles
+    const T *isb2pi;  // 1 / (2 pi sin thetabar_j)
+    const T *idthb;   // 1 / (thetabar_j - thetabar_{j-1})
+    const T *ab_int;  // lossy-layer factor at rho = i
+    const T *ab_half; // lossy-layer factor at rho = i + 1/2
+};
+
+// ------------------------------------------------------------------
+// Field kernels
+// ------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ p, size_t n, T v)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+// B += hc * circulation(E) / area for B_r (i, j+1/2), B_th (i+1/2, j),
+// B_ph (i+1/2, j+1/2).  B_r is held at zero on the conductors and B_th on
+// the axis.
+template <typename T>
+__global__ __launch_bounds__(256) void k_faraday(Fields<T> f, Layout L, Metric<T> m, T hc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int nr = L.nr, nth = L.nth;
+    if (i > nr || j > nth) return;
+    const T *Er = f.c[cER], *Eth = f.c[cETH], *Eph = f.c[cEPH];
+    if (i >= 1 && i < nr && j < nth) {
+        const T circ = Eph[L.at(i, j)] * m.s[j] - Eph[L.at(i, j + 1)] * m.s[j + 1];
+        f.c[cBR][L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
+    }
+    if (i < nr && j >= 1 && j < nth) {
+        const T circ = Eph[L.at(i + 1, j)] * m.r_node[i + 1 + L.G] - Eph[L.at(i, j)] * m.r_node[i + L.G];
+        f.c[cBTH][L.at(i, j)] += hc * circ * m.idr2[i];
+    }
+    if (i < nr && j < nth) {
+        const T a = Eth[L.at(i, j)] * m.r_node[i + L.G] - Eth[L.at(i + 1, j)] * m.r_node[i + 1 + L.G];
+        const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * m.dr[i] * m.idth[j];
+        f.c[cBPH][L.at(i, j)] += hc * (a - b) * m.idr2[i];
+    }
+}
+
+// E += (c circulation(B) - F) / area, then the lossy-layer factor on E.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ampere(Fields<T> f, const T *__restrict__ Fr, const T *__restrict__ Fth,
+                                                const T *__restrict__ Fph, Layout L, Metric<T> m, T c)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int nr = L.nr, nth = L.nth;
+    if (i > nr || j > nth) return;
+    const T *Br = f.c[cBR], *Bth = f.c[cBTH], *Bph = f.c[cBPH];
+    if (i < nr) {
+        const T t1 = j < nth ? m.sb[j] * Bph[L.at(i, j)] : (T)0;
+        const T t0 = j > 0 ? m.sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
+        T &e = f.c[cER][L.at(i, j)];
+        e = (e + (c * (t1 - t0) * m.invrb[i] - Fr[L.at(i, j)] * m.invA[i]) * m.idkb[j]) * m.ab_half[i];
+    }
+    if (i >= 1 && i < nr && j < nth) {
+        const T circ = m.rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - m.rb[i + L.G] * Bph[L.at(i, j)];
+        T &e = f.c[cETH][L.at(i, j)];
+        e = (e + (c * circ - Fth[L.at(i, j)] * m.isb2pi[j]) * m.idrb2[i]) * m.ab_int[i];
+    }
+    if (i >= 1 && i < nr && j >= 1 && j < nth) {
+        const T a = m.rb[i + L.G] * Bth[L.at(i, j)] - m.rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
+        const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * m.drb[i] * m.idthb[j];
+        T &e = f.c[cEPH][L.at(i, j)];
+        e = (e + (c * (a - b) - Fph[L.at(i, j)] * m.idthb[j]) * m.idrb2[i]) * m.ab_int[i];
+    }
+}
+
+// Lossy layer on B, rows i0..nr only (the factor is 1 elsewhere).
+template <typename T>
+__global__ __launch_bounds__(256) void k_absorb_b(Fields<T> f, Layout L, Metric<T> m, int i0)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = i0 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.nr || j > L.nth) return;
+    if (j < L.nth) f.c[cBR][L.at(i, j)] *= m.ab_int[i];
+    if (i < L.nr) {
+        f.c[cBTH][L.at(i, j)] *= m.ab_half[i];
+        if (j < L.nth) f.c[cBPH][L.at(i, j)] *= m.ab_half[i];
+    }
+}
+
+// One pass of the 1-2-1 filter on up to three arrays (blockIdx.z picks one).
+// kind 0: integer-j positions (F_r, F_ph, node charge), kind 1: half-integer
+// j (F_th).  In theta the array is extended by zeros, filtered, and what
+// spilled across a pole is folded back onto its mirror image, with a plus
+// sign for integer-j components and a minus sign for the theta component;
+// radially the array is extended by zeros beyond rows [-G, last_row].
+struct FilterSet {
+    const void *src[3];
+    void *dst[3];
+    int kind[3];
+    int last_row[3];
+};
+
+template <typename T>
+__device__ inline T theta_pass(const T *__restrict__ a, const Layout &L, int i, int j, int kind)
+{
+    const int nth = L.nth;
+    const int ncol = kind ? nth : nth + 1;
+    const T *row = a + L.at(i, 0);
+    T v = (T)0.5 * row[j];
+    if (j > 0) v += (T)0.25 * row[j - 1];
+    if (j + 1 < ncol) v += (T)0.25 * row[j + 1];
+    if (kind == 0) {
+        if (j == 1) v += (T)0.25 * row[0];
+        if (j == nth - 1) v += (T)0.25 * row[nth];
+    } else {
+        if (j == 0) v -= (T)0.25 * row[0];
+        if (j == nth - 1) v -= (T)0.25 * row[nth - 1];
+    }
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter(FilterSet fs, Layout L)
+{
+    const int z = blockIdx.z;
+    const int kind = fs.kind[z];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = -L.G + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int ncol = kind ? L.nth : L.nth + 1;
+    const int last = fs.last_row[z];
+    if (i > last || j >= ncol) return;
+    const T *a = (const T *)fs.src[z];
+    T v = (T)0.5 * theta_pass(a, L, i, j, kind);
+    if (i > -L.G) v += (T)0.25 * theta_pass(a, L, i - 1, j, kind);
+    if (i < last) v += (T)0.25 * theta_pass(a, L, i + 1, j, kind);
+    ((T *)fs.dst[z])[L.at(i, j)] = v;
+}
+
+// ------------------------------------------------------------------
+// Particle push
+// ------------------------------------------------------------------
+
+template <typename T>
+struct PushArgs {
+    Layout L;
+    Fields<T> f;          // E, B (read) and F (deposit target)
+    Background bg;
+    int r_kind, th_kind, mover, n_filt;
+    T c, dxi, dr_lin, nth_f, two_over_nth, pi_over_nth, eps0, inv_rl;
+    const T *r_node;      // r(i) at [i + G]
+    const T *k_node;      // cos theta_j
+    uint32_t *cell;
+    T *dx, *dy, *ur, *ut, *up;
+    const T *w;
+    const unsigned long long *n_total;
+    unsigned long long *n_dead;
+    int *status;
+    int lds_cap;          // entries per LDS plane, 0 = gather/deposit in global memory
+};
+
+template <typename T>
+struct GlobalView {
+    const Fields<T> *f;
+    Layout L;
+    __device__ T get(int c, int i, int j) const { return f->c[c][L.at(i, j)]; }
+    // half-integer-j component continued across the axis with parity sgn
+    __device__ T geth(int c, int i, int j, T sgn) const
+    {
+        if (j < 0) return sgn * f->c[c][L.at(i, 0)];
+        if (j >= L.nth) return sgn * f->c[c][L.at(i, L.nth - 1)];
+        return f->c[c][L.at(i, j)];
+    }
+};
+
+template <typename T>
+struct GlobalDep {
+    T *F[3];
+    Layout L;
+    __device__ void add(int c, int i, int j, T v) const { unsafeAtomicAdd(&F[c][L.at(i, j)], v); }
+};
+
+template <typename T>
+struct LdsView {
+    const T *s;
+    int cap, i0, j0, C;
+    __device__ T get(int c, int i, int j) const { return s[c * cap + (i - i0) * C + (j - j0)]; }
+    __device__ T geth(int c, int i, int j, T) const { return get(c, i, j); } // mirror staged
+};
+
+template <typename T>
+struct LdsDep {
+    T *s;
+    int cap, i0, j0, C;
+    __device__ void add(int c, int i, int j, T v) const { atomicAdd(&s[c * cap + (i - i0) * C + (j - j0)], v); }
+};
+
+template <typename T>
+__device__ inline T bilin(T v00, T v10, T v01, T v11, T x, T y)
+{
+    return ((T)1 - y) * (((T)1 - x) * v00 + x * v10) + y * (((T)1 - x) * v01 + x * v11);
+}
+
+// Plasma field at offset (fx, fy) of cell (i, j): bilinear in grid
+// coordinates from each component's own staggered lattice; half-integer-j
+// components continue across the axis with their parity (r even, theta and
+// phi odd).
+template <typename T, typename V>
+__device__ inline void gather(const V &v, int i, int j, T fx, T fy, T E[3], T B[3])
+{
+    int ih = i, jh = j;
+    T hx = fx - (T)0.5, hy = fy - (T)0.5;
+    if (hx < (T)0) { ih = i - 1; hx += (T)1; }
+    if (hy < (T)0) { jh = j - 1; hy += (T)1; }
+    E[0] += bilin(v.get(cER, ih, j), v.get(cER, ih + 1, j), v.get(cER, ih, j + 1), v.get(cER, ih + 1, j + 1), hx, fy);
+    E[1] += bilin(v.geth(cETH, i, jh, (T)-1), v.geth(cETH, i + 1, jh, (T)-1), v.geth(cETH, i, jh + 1, (T)-1),
+                  v.geth(cETH, i + 1, jh + 1, (T)-1), fx, hy);
+    E[2] += bilin(v.get(cEPH, i, j), v.get(cEPH, i + 1, j), v.get(cEPH, i, j + 1), v.get(cEPH, i + 1, j + 1), fx, fy);
+    B[0] += bilin(v.geth(cBR, i, jh, (T)1), v.geth(cBR, i + 1, jh, (T)1), v.geth(cBR, i, jh + 1, (T)1),
+                  v.geth(cBR, i + 1, jh + 1, (T)1), fx, hy);
+    B[1] += bilin(v.get(cBTH, ih, j), v.get(cBTH, ih + 1, j), v.get(cBTH, ih, j + 1), v.get(cBTH, ih + 1, j + 1), hx, fy);
+    B[2] += bilin(v.geth(cBPH, ih, jh, (T)-1), v.geth(cBPH, ih + 1, jh, (T)-1), v.geth(cBPH, ih, jh + 1, (T)-1),
+                  v.geth(cBPH, ih + 1, jh + 1, (T)-1), hx, hy);
+}
+
+// Charge flux of a cell-sized cloud moving on a straight piece inside cell
+// (i, j), local coordinates (xa, ya) -> (xb, yb): the integral of the
+// bilinear weights along the piece.
+template <typename T, typename D>
+__device__ inline void vb_piece(const D &d, int i, int j, T xa, T ya, T xb, T yb, T Q)
+{
+    const T mx = (T)0.5 * (xa + xb), my = (T)0.5 * (ya + yb);
+    const T qx = Q * (xb - xa), qy = Q * (yb - ya);
+    d.add(0, i, j, qx * ((T)1 - my));
+    d.add(0, i, j + 1, qx * my);
+    d.add(1, i, j, qy * ((T)1 - mx));
+    d.add(1, i + 1, j, qy * mx);
+}
+
+// Villasenor-Buneman deposit of the move (x0, y0) -> (x1, y1), both in the
+// frame of cell (i, j) (start in [0,1)^2, end within one cell of it): cut at
+// the cell faces it crosses, each piece deposited in its own cell; plus the
+// ring charge Q dphi / 2 pi crossing a meridional half-plane, assigned
+// bilinearly at the midpoint of the move.
+template <typename T, typename D>
+__device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0, T x1, T y1, T Q, T dphi)
+{
+    int cx = 0, cy = 0;
+    T X = 0, Y = 0;
+    if (x1 >= (T)1) { cx = 1; X = (T)1; } else if (x1 < (T)0) { cx = -1; X = (T)0; }
+    if (y1 >= (T)1 && j < nth - 1) { cy = 1; Y = (T)1; } else if (y1 < (T)0) { cy = -1; Y = (T)0; }
+    T px[4], py[4];
+    int np = 0;
+    px[np] = x0; py[np] = y0; ++np;
+    if (cx && cy) {
+        const T tx = (X - x0) / (x1 - x0), ty = (Y - y0) / (y1 - y0);
+        if (tx < ty) {
+            px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
+            px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
+        } else if (ty < tx) {
+            px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
+            px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
+        } else {
+            px[np] = X; py[np] = Y; ++np;
+        }
+    } else if (cx) {
+        const T tx = (X - x0) / (x1 - x0);
+        px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
+    } else if (cy) {
+        const T ty = (Y - y0) / (y1 - y0);
+        px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
+    }
+    px[np] = x1; py[np] = y1; ++np;
+    for (int q = 0; q + 1 < np; ++q) {
+        const T mx = (T)0.5 * (px[q] + px[q + 1]), my = (T)0.5 * (py[q] + py[q + 1]);
+        const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
+        int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
+        if (j + dj > nth - 1) dj = nth - 1 - j;
+        vb_piece(d, i + di, j + dj, px[q] - (T)di, py[q] - (T)dj, px[q + 1] - (T)di, py[q + 1] - (T)dj, Q);
+    }
+    const T mx = (T)0.5 * (x0 + x1), my = (T)0.5 * (y0 + y1);
+    const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
+    int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
+    if (j + dj > nth - 1) dj = nth - 1 - j;
+    const T fx = mx - (T)di, fy = my - (T)dj;
+    const T q = Q * dphi * (T)(0.5 / kPi);
+    d.add(2, i + di, j + dj, q * ((T)1 - fx) * ((T)1 - fy));
+    d.add(2, i + di + 1, j + dj, q * fx * ((T)1 - fy));
+    d.add(2, i + di, j + dj + 1, q * ((T)1 - fx) * fy);
+    d.add(2, i + di + 1, j + dj + 1, q * fx * fy);
+}
+
+template <typename T>
+__device__ inline T below_one();
+template <>
+__device__ inline float below_one<float>() { return 0x1.fffffep-1f; }
+template <>
+__device__ inline double below_one<double>() { return 0x1.fffffffffffffp-1; }
+
+// One particle: gather, push, move with cancellation-free local increments,
+// deposit, particle boundaries.
+template <typename T, typename V, typename D>
+__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, size_t idx, uint32_t cl)
+{
+    const int nr = p.L.nr, nth = p.L.nth;
+    const int i = cell_i(cl), j = cell_j(cl);
+    const T fx = p.dx[idx], fy = p.dy[idx];
+    const T w = p.w[idx];
+    T r = p.r_node[i + p.L.G];
+    if (p.r_kind == 0) r *= exp(fx * p.dxi);
+    else r += fx * p.dr_lin;
+    T k, s;
+    if (p.th_kind == 0) {
+        const T y = (T)j + fy;
+        k = p.k_node[j] - fy * p.two_over_nth;
+        s = p.two_over_nth * sqrt(fmax(y * (p.nth_f - y), (T)0));
+    } else {
+        const T th = ((T)j + fy) * p.pi_over_nth;
+        s = sin(th);
+        k = cos(th);
+    }
+    const T u0 = p.ur[idx], u1 = p.ut[idx], u2 = p.up[idx];
+    // Cartesian frame at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = (0, 1, 0)
+    T uc[3] = {s * u0 + k * u1, u2, k * u0 - s * u1};
+    const bool outer = i > nr || (i == nr && fx > (T)0); // beyond the outer conductor: ballistic
+    const bool inner = i < 0;                            // inside the star: corotation field only
+    const T eps = w > (T)0 ? p.eps0 : (w < (T)0 ? -p.eps0 : (T)0);
+    if (!outer && eps != (T)0) {
+        T E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+        if (!inner) gather(view, i, j, fx, fy, E, B);
+        add_background(p.bg, p.inv_rl, inner, r, k, s, E, B);
+        const T Ec[3] = {s * E[0] + k * E[1], E[2], k * E[0] - s * E[1]};
+        const T Bc[3] = {s * B[0] + k * B[1], B[2], k * B[0] - s * B[1]};
+        if (p.mover == 0) vay_push(uc, Ec, Bc, eps);
+        else boris_push(uc, Ec, Bc, eps);
+    }
+    // displacement over the step, relative to r
+    const T vg = p.c / sqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+    const T ir = (T)1 / r;
+    const T ex = uc[0] * vg * ir, ey = uc[1] * vg * ir, ez = uc[2] * vg * ir;
+    const T xs = s + ex, zs = k + ez;                    // (R', Z') / r
+    const T q = (T)2 * (s * ex + k * ez) + ex * ex + ey * ey + ez * ez;
+    const T sq = sqrt((T)1 + q);                         // r' / r
+    const T eta = q / ((T)1 + sq);                       // r' / r - 1
+    const T dX = p.r_kind == 0 ? log1p(eta) / p.dxi : r * eta / p.dr_lin;
+    const T Rn = sqrt(xs * xs + ey * ey);
+    const T isq = (T)1 / sq;
+    T dY;
+    if (p.th_kind == 0) dY = (T)-0.5 * p.nth_f * ((ez - k * eta) * isq);
+    else dY = atan2(Rn * k - zs * s, Rn * s + zs * k) / p.pi_over_nth;
+    const T X1 = fx + dX;
+    T Y1 = fy + dY;
+    if ((T)j + Y1 < (T)0) Y1 = -(T)j;                    // reflection at the poles: y' in [0, nth]
+    if ((T)j + Y1 > p.nth_f) Y1 = p.nth_f - (T)j;
+    if (!(fabs(X1 - fx) < (T)1 && fabs(Y1 - fy) < (T)1)) { // CFL (or a non-finite value)
+        atomicOr(p.status, 1);
+        return;
+    }
+    T cph = (T)1, sph = (T)0;
+    if (Rn > (T)0) { cph = xs / Rn; sph = ey / Rn; }
+    vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w, atan2(sph, cph));
+    const T k1 = zs * isq, s1 = Rn * isq;
+    const T ux = cph * uc[0] + sph * uc[1], uy = -sph * uc[0] + cph * uc[1], uz = uc[2];
+    int ni = i, nj = j;
+    T nx = X1, ny = Y1;
+    if (nx >= (T)1) { ++ni; nx -= (T)1; }
+    else if (nx < (T)0) { --ni; nx += (T)1; if (nx >= (T)1) nx = below_one<T>(); }
+    if (ny >= (T)1) { ++nj; ny -= (T)1; }
+    else if (ny < (T)0) { --nj; ny += (T)1; if (ny >= (T)1) ny = below_one<T>(); }
+    if (nj > nth - 1) { nj = nth - 1; ny = (T)1; }      // y' = nth belongs to the last cell
+    p.dx[idx] = nx;
+    p.dy[idx] = ny;
+    p.ur[idx] = s1 * ux + k1 * uz;
+    p.ut[idx] = k1 * ux - s1 * uz;
+    p.up[idx] = uy;
+    const int lim = p.n_filt + 1;                        // whole filtered shape inside a conductor
+    if (ni < -lim || ni > nr + lim || (ni == nr + lim && nx > (T)0)) {
+        p.cell[idx] = kDead;
+        atomicAdd(p.n_dead, 1ull);
+    } else {
+        p.cell[idx] = pack_cell(ni, nj);
+    }
+}
+
+__device__ inline int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// One work-group per chunk of 256 * PPT consecutive (cell-sorted) particles.
+// The chunk's cell bounding box, widened by one cell below and two above
+// (gather stencils and one-cell moves), is staged in LDS when it fits:
+// six field planes with the axis mirror applied, and three face-charge
+// planes that collect the chunk's deposits with LDS atomics and are flushed
+// with one global atomic per non-zero entry.  Chunks that do not fit (an
+// unsorted tail) gather and deposit in global memory.  Work-group b serves
+// the chunk range of XCD b % 8 so that neighbouring chunks share an L2.
+template <typename T, int PPT>
+__global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    __shared__ int red[4][4];
+    constexpr int CH = 256 * PPT;
+    const unsigned long long n = *p.n_total;
+    const long long nch = (long long)((n + CH - 1) / CH);
+    const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+    const long long lo = nch * xcd / 8, hi = nch * (xcd + 1) / 8;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int cap = p.lds_cap;
+    const int nth = p.L.nth;
+    for (long long ch = lo + loc; ch < hi; ch += nloc) {
+        const size_t base = (size_t)ch * CH;
+        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+        if (cap > 0) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const size_t idx = base + tid + 256 * q;
+                const uint32_t c = idx < n ? p.cell[idx] : kDead;
+                if (c != kDead) {
+                    const int ci = cell_i(c), cj = cell_j(c);
+                    imin = min(imin, ci); imax = max(imax, ci);
+                    jmin = min(jmin, cj); jmax = max(jmax, cj);
+                }
+            }
+        }
+        bool use = false;
+        int i0 = 0, j0 = 0, C = 0;
+        if (cap > 0) {
+            imin = wave_min(imin); imax = wave_max(imax);
+            jmin = wave_min(jmin); jmax = wave_max(jmax);
+            if (lane == 0) { red[wv][0] = imin; red[wv][1] = imax; red[wv][2] = jmin; red[wv][3] = jmax; }
+            __syncthreads();
+            imin = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+            imax = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1]));
+            jmin = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+            jmax = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
+            __syncthreads();
+            if (imin <= imax) {
+                const int R = imax - imin + 4;
+                C = jmax - jmin + 4;
+                use = (long long)R * C <= cap;
+                i0 = imin - 1;
+                j0 = jmin - 1;
+            }
+        }
+        if (use) {
+            const int RC = (imax - imin + 4) * C;
+            for (int e = tid; e < RC; e += 256) {
+                const int rr = e / C, cc = e - rr * C;
+                const int gi = i0 + rr, gj = j0 + cc;
+                const bool vi = gj >= 0 && gj <= nth;
+                int hj = gj;
+                T so = (T)1;
+                if (gj < 0) { hj = -1 - gj; so = (T)-1; }
+                else if (gj >= nth) { hj = 2 * nth - 1 - gj; so = (T)-1; }
+                const bool vh = hj >= 0 && hj < nth;
+                sm[cER * cap + e] = vi ? p.f.c[cER][p.L.at(gi, gj)] : (T)0;
+                sm[cEPH * cap + e] = vi ? p.f.c[cEPH][p.L.at(gi, gj)] : (T)0;
+                sm[cBTH * cap + e] = vi ? p.f.c[cBTH][p.L.at(gi, gj)] : (T)0;
+                sm[cETH * cap + e] = vh ? so * p.f.c[cETH][p.L.at(gi, hj)] : (T)0;
+                sm[cBR * cap + e] = vh ? p.f.c[cBR][p.L.at(gi, hj)] : (T)0;
+                sm[cBPH * cap + e] = vh ? so * p.f.c[cBPH][p.L.at(gi, hj)] : (T)0;
+                sm[6 * cap + e] = (T)0;
+                sm[7 * cap + e] = (T)0;
+                sm[8 * cap + e] = (T)0;
+            }
+            __syncthreads();
+            const LdsView<T> view{sm, cap, i0, j0, C};
+            const LdsDep<T> dep{sm + 6 * cap, cap, i0, j0, C};
+#pragma unroll 1
+            for (int q = 0; q < PPT; ++q) {
+                const size_t idx = base + tid + 256 * q;
+                const uint32_t c = idx < n ? p.cell[idx] : kDead;
+                if (c != kDead) push_particle(p, view, dep, idx, c);
+            }
+            __syncthreads();
+            for (int e = tid; e < 3 * RC; e += 256) {
+                const int comp = e / RC, ee = e - comp * RC;
+                const T v = sm[(6 + comp) * cap + ee];
+                if (v != (T)0) {
+                    const int rr = ee / C, cc = ee - rr * C;
+                    unsafeAtomicAdd(&p.f.c[cFR + comp][p.L.at(i0 + rr, j0 + cc)], v);
+                }
+            }
+            __syncthreads();
+        } else {
+            const GlobalView<T> view{&p.f, p.L};
+            const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
+#pragma unroll 1
+            for (int q = 0; q < PPT; ++q) {
+                const size_t idx = base + tid + 256 * q;
+                const uint32_t c = idx < n ? p.cell[idx] : kDead;
+                if (c != kDead) push_particle(p, view, dep, idx, c);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------
+// Surface injection (one work-group of 1024 threads)
+// ------------------------------------------------------------------
+
+template <typename T>
+struct InjectArgs {
+    Layout L;
+    const T *Er;
+    Background bg;
+    double inv_rl;        // Omega(t_{n+1}) / c
+    double rb0;           // r(1/2): position of E_r next to the conductor
+    const double *kn, *sn; // cos / sin theta_j
+    const double *Aj;     // dual face area of node j on the inner conductor
+    double f_inj, q_inj;
+    double *carry;
+    uint64_t seed, step;
+    uint32_t *cell;
+    T *dx, *dy, *ur, *ut, *up, *w;
+    uint64_t *id;         // may be null
+    unsigned long long *n_total, *n_injected;
+    long long capacity;
+    int *status;
+};
+
+constexpr int kInjMaxPer = 8; // nth + 1 <= 8192
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_inject(InjectArgs<T> a)
+{
+    __shared__ long long scan[1024];
+    __shared__ int ok;
+    const int tid = threadIdx.x;
+    const int nth = a.L.nth, nodes = nth + 1;
+    const int per = (nodes + 1023) / 1024;
+    const int j0 = tid * per, j1 = min(j0 + per, nodes);
+    long long m[kInjMaxPer];
+    long long mine = 0;
+    for (int jj = j0; jj < j1; ++jj) {
+        double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+        add_background(a.bg, a.inv_rl, false, a.rb0, a.kn[jj], a.sn[jj], E, B);
+        const double sigma = (double)a.Er[a.L.at(0, jj)] + E[0];
+        const double cnew = a.carry[jj] + a.f_inj * fabs(sigma) * a.Aj[jj] / a.q_inj;
+        const double fl = floor(cnew);
+        a.carry[jj] = cnew - fl;
+        m[jj - j0] = (long long)fl;
+        mine += (long long)fl;
+    }
+    scan[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const long long v = tid >= o ? scan[tid - o] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    const long long total = scan[1023];
+    long long off = scan[tid] - mine;
+    const unsigned long long nbase = *a.n_total;
+    if (tid == 0) ok = (long long)nbase + 2 * total <= a.capacity;
+    __syncthreads();
+    if (!ok) {
+        if (tid == 0) atomicOr(a.status, 2);
+        return;
+    }
+    for (int jj = j0; jj < j1; ++jj) {
+        const double ylo = jj - 0.5 < 0.0 ? 0.0 : jj - 0.5;
+        const double yhi = jj + 0.5 > nth ? (double)nth : jj + 0.5;
+        for (long long kk = 0; kk < m[jj - j0]; ++kk) {
+            uint64_t x[4] = {a.step, (uint64_t)jj, (uint64_t)kk, 0};
+            philox4x64(x, a.seed, 0x50494353ull);
+            const double U = (double)(x[0] >> 11) * 0x1.0p-53;
+            const double y = ylo + U * (yhi - ylo);
+            int jc = (int)floor(y);
+            if (jc > nth - 1) jc = nth - 1;
+            const T fy = (T)(y - jc);
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const size_t d = nbase + 2 * (size_t)(off + kk) + sgn;
+                a.cell[d] = pack_cell(0, jc);
+                a.dx[d] = (T)0.5;
+                a.dy[d] = fy;
+                a.ur[d] = a.ut[d] = a.up[d] = (T)0;
+                a.w[d] = sgn == 0 ? (T)a.q_inj : (T)-a.q_inj;
+                if (a.id)
+                    a.id[d] = 0x8000000000000000ull | (a.step << 36) | ((uint64_t)jj << 20) | ((uint64_t)kk << 1) |
+                              (uint64_t)sgn;
+            }
+        }
+        off += m[jj - j0];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        *a.n_total = nbase + 2 * total;
+        *a.n_injected += 2 * total;
+    }
+}
+
+// ------------------------------------------------------------------
+// Counting sort by tile
+// ------------------------------------------------------------------
+
+struct TileMap {
+    int G, tile_r, tile_th, ntj, n_keys;
+    __device__ int key(uint32_t c) const
+    {
+        if (c == kDead) return n_keys;
+        const int ti = (cell_i(c) + G) / tile_r;
+        int tj = cell_j(c) / tile_th;
+        if (ti & 1) tj = ntj - 1 - tj; // serpentine: consecutive tiles share an edge
+        return ti * ntj + tj;
+    }
+};
+
+__device__ inline unsigned long long lanemask_le(int lane)
+{
+    return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+
+// Histogram of tile keys; runs of equal keys inside a wave (the common case
+// for particles sorted a few steps ago) cost one atomic per run.
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *__restrict__ cell,
+                                                   const unsigned long long *n_total, TileMap tm,
+                                                   unsigned int *__restrict__ counts)
+{
+    const unsigned long long n = *n_total;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long b = blockIdx.x * (unsigned long long)blockDim.x; b < n; b += stride) {
+        const unsigned long long idx = b + threadIdx.x;
+        const int key = idx < n ? tm.key(cell[idx]) : INT_MAX;
+        const int prev = __shfl_up(key, 1);
+        const bool head = lane == 0 || key != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long after = heads & ~lanemask_le(lane);
+        const int next = after ? __ffsll((long long)after) - 1 : 64;
+        if (head && key != INT_MAX) atomicAdd(&counts[key], (unsigned int)(next - lane));
+    }
+}
+
+// Exclusive scan of counts[0..n_keys] (the last key collects deleted
+// particles) into offsets; n_total becomes the number of live particles.
+__global__ __launch_bounds__(1024) void k_sort_scan(const unsigned int *__restrict__ counts, int n_keys,
+                                                    unsigned long long *__restrict__ offsets,
+                                                    unsigned long long *n_total, unsigned long long *n_live_out)
+{
+    __shared__ unsigned long long s[1024];
+    const int tid = threadIdx.x;
+    const int per = (n_keys + 1 + 1023) / 1024;
+    const int a = tid * per, b = min(a + per, n_keys + 1);
+    unsigned long long mine = 0;
+    for (int q = a; q < b; ++q) mine += counts[q];
+    s[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const unsigned long long v = tid >= o ? s[tid - o] : 0;
+        __syncthreads();
+        s[tid] += v;
+        __syncthreads();
+    }
+    unsigned long long run = s[tid] - mine;
+    for (int q = a; q < b; ++q) {
+        offsets[q] = run;
+        run += counts[q];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // offsets[n_keys] = first slot of the deleted ones = number of live particles
+        *n_live_out = s[1023] - counts[n_keys];
+    }
+}
+
+// Live particles at the start of a step, accumulated: the particle-steps
+// actually advanced.
+__global__ void k_count_live(unsigned long long *ctr) { ctr[5] += ctr[0] - ctr[1]; }
+
+// After the scatter: live count becomes the particle count; deletions since
+// the last sort move to the running total.  ctr = {total, dead since sort,
+// deleted, injected, live}.
+__global__ void k_finish_sort(unsigned long long *ctr)
+{
+    ctr[2] += ctr[1];
+    ctr[1] = 0;
+    ctr[0] = ctr[4];
+}
+
+template <typename T>
+struct SortArgs {
+    const uint32_t *cell;
+    const T *a[6];
+    const uint64_t *id;
+    uint32_t *cell_o;
+    T *a_o[6];
+    uint64_t *id_o;
+    const unsigned long long *n_total;
+    const unsigned long long *offsets;
+    unsigned int *cursor;
+    TileMap tm;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sort_scatter(SortArgs<T> s)
+{
+    const unsigned long long n = *s.n_total;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long b = blockIdx.x * (unsigned long long)blockDim.x; b < n; b += stride) {
+        const unsigned long long idx = b + threadIdx.x;
+        const uint32_t c = idx < n ? s.cell[idx] : kDead;
+        const int key = idx < n ? s.tm.key(c) : INT_MAX;
+        const int prev = __shfl_up(key, 1);
+        const bool head = lane == 0 || key != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long after = heads & ~lanemask_le(lane);
+        const int next = after ? __ffsll((long long)after) - 1 : 64;
+        const bool live = key != INT_MAX && key != s.tm.n_keys;
+        unsigned int got = 0;
+        if (head && live) got = atomicAdd(&s.cursor[key], (unsigned int)(next - lane));
+        const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
+        got = __shfl(got, hl);
+        if (live) {
+            const unsigned long long d = s.offsets[key] + got + (lane - hl);
+            s.cell_o[d] = c;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s.a_o[q][d] = s.a[q][idx];
+            if (s.id) s.id_o[d] = s.id[idx];
+        }
+    }
+}
+
+// ------------------------------------------------------------------
+// Particle load (FP64 absolute coordinates -> cell + offsets)
+// ------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_load(const double *__restrict__ src, const uint64_t *__restrict__ ids,
+                                              long long n, long long at, int nth, uint32_t *cell, T *dx, T *dy,
+                                              T *ur, T *ut, T *up, T *w, uint64_t *id)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const double x = src[q], y = src[n + q];
+        const int i = (int)floor(x);
+        int j = (int)floor(y);
+        if (j > nth - 1) j = nth - 1;
+        T fx = (T)(x - i), fy = (T)(y - j);
+        if (fx >= (T)1) fx = below_one<T>();
+        if (fy > (T)1) fy = (T)1;
+        if (j < nth - 1 && fy >= (T)1) fy = below_one<T>();
+        const long long d = at + q;
+        cell[d] = pack_cell(i, j);
+        dx[d] = fx;
+        dy[d] = fy;
+        ur[d] = (T)src[2 * n + q];
+        ut[d] = (T)src[3 * n + q];
+        up[d] = (T)src[4 * n + q];
+        w[d] = (T)src[5 * n + q];
+        if (id) id[d] = ids ? ids[q] : (uint64_t)d;
+    }
+}
+
+// ------------------------------------------------------------------
+// Gauss diagnostic in FP64
+// ------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict__ cell, const T *__restrict__ dx,
+                                                     const T *__restrict__ dy, const T *__restrict__ w,
+                                                     const unsigned long long *n_total, Layout L, double *rho)
+{
+    const unsigned long long n = *n_total;
+    for (unsigned long long q = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; q < n;
+         q += (unsigned long long)gridDim.x * blockDim.x) {
+        const uint32_t c = cell[q];
+        if (c == kDead) continue;
+        const int i = cell_i(c), j = cell_j(c);
+        const double fx = dx[q], fy = dy[q], Q = w[q];
+        unsafeAtomicAdd(&rho[L.at(i, j)], Q * (1 - fx) * (1 - fy));
+        unsafeAtomicAdd(&rho[L.at(i + 1, j)], Q * fx * (1 - fy));
+        unsafeAtomicAdd(&rho[L.at(i, j + 1)], Q * (1 - fx) * fy);
+        unsafeAtomicAdd(&rho[L.at(i + 1, j + 1)], Q * fx * fy);
+    }
+}
+
+// Closed-surface flux of E out of the dual cell of node (i, j), i = 1..nr-1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gauss_flux(const T *__restrict__ Er, const T *__restrict__ Eth, Layout L,
+                                                    const double *__restrict__ Ar,  // 2 pi rbar_i^2, [i + G]
+                                                    const double *__restrict__ dkb, // cos thetabar_{j-1} - cos thetabar_j
+                                                    const double *__restrict__ At,  // pi (rbar_i^2 - rbar_{i-1}^2)
+                                                    const double *__restrict__ sb,  // sin thetabar_j
+                                                    double *__restrict__ G)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.nr || j > L.nth) return;
+    double flux = 0.0;
+    if (i >= 1 && i < L.nr) {
+        flux = (double)Er[L.at(i, j)] * Ar[i + L.G] * dkb[j] - (double)Er[L.at(i - 1, j)] * Ar[i - 1 + L.G] * dkb[j];
+        if (j < L.nth) flux += (double)Eth[L.at(i, j)] * At[i] * sb[j];
+        if (j > 0) flux -= (double)Eth[L.at(i, j - 1)] * At[i] * sb[j - 1];
+    }
+    G[(size_t)i * (L.nth + 1) + j] = flux;
+}
+
+} // namespace pic

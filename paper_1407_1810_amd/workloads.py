@@ -77,30 +77,66 @@ def mj_momenta(rng: np.random.Generator, n: int, theta: float):
     return umag * mu, umag * st * np.cos(ph), umag * st * np.sin(ph)
 
 
+def _pair_chunk(out, lo, hi, p, pairs_per_cell, theta_T, weight, seed, chunk_id, i0, nj):
+    """Fill pairs lo..hi-1 (pair index) of the output arrays; the chunk has
+    its own Philox key so the result does not depend on how chunks are
+    scheduled."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, chunk_id + 1]))
+    m = hi - lo
+    cells = np.arange(lo, hi, dtype=np.int64) // pairs_per_cell
+    cells = cells[rng.permutation(m)]
+    xp = (i0 + cells // nj) + rng.random(m)
+    yp = (cells % nj) + rng.random(m)
+    a, b = 2 * lo, 2 * hi
+    out["x"][a:b:2] = xp
+    out["x"][a + 1:b:2] = xp
+    out["y"][a:b:2] = yp
+    out["y"][a + 1:b:2] = yp
+    if theta_T > 0:
+        ur, ut, up = mj_momenta(rng, 2 * m, theta_T)
+        out["ur"][a:b] = ur
+        out["ut"][a:b] = ut
+        out["up"][a:b] = up
+    else:
+        out["ur"][a:b] = 0.0
+        out["ut"][a:b] = 0.0
+        out["up"][a:b] = 0.0
+    out["w"][a:b:2] = weight
+    out["w"][a + 1:b:2] = -weight
+    out["id"][a:b] = np.arange(a, b, dtype=np.uint64)
+
+
 def pair_plasma(p: dict, pairs_per_cell: int, theta_T: float, weight: float, seed: int,
-                i_range=None, j_range=None, shuffle: bool = True) -> dict:
-    """Co-located electron/positron pairs, positions uniform in each cell of
-    rows i_range x columns j_range (default: the whole grid), momenta
-    Maxwell-Juttner.  Returns float64 arrays x, y, ur, ut, up, w and uint64 id."""
-    rng = np.random.Generator(np.random.Philox(seed))
+                i_range=None, j_range=None, chunk_pairs: int = 1 << 20, threads: int | None = None) -> dict:
+    """Co-located electron/positron pairs (positron first), positions uniform
+    in each cell of rows i_range x columns j_range (default: the whole grid),
+    momenta Maxwell-Juttner; cell order is shuffled within each chunk of
+    `chunk_pairs` pairs.  Returns float64 arrays x, y, ur, ut, up, w and
+    uint64 id = array index."""
+    import concurrent.futures as cf
+    import os
     i0, i1 = i_range if i_range else (0, p["nr"])
     j0, j1 = j_range if j_range else (0, p["nth"])
     ni, nj = i1 - i0, j1 - j0
     npair = ni * nj * pairs_per_cell
-    cell = np.repeat(np.arange(ni * nj, dtype=np.int64), pairs_per_cell)
-    if shuffle:
-        cell = rng.permutation(cell)
-    xp = (i0 + cell // nj) + rng.random(npair)
-    yp = (j0 + cell % nj) + rng.random(npair)
-    del cell
     n = 2 * npair
-    x = np.repeat(xp, 2)
-    y = np.repeat(yp, 2)
-    del xp, yp
-    ur, ut, up = mj_momenta(rng, n, theta_T) if theta_T > 0 else (np.zeros(n), np.zeros(n), np.zeros(n))
-    w = np.tile(np.array([weight, -weight]), npair)
-    ids = np.arange(n, dtype=np.uint64)
-    return dict(x=x, y=y, ur=ur, ut=ut, up=up, w=w, id=ids)
+    out = {k: np.empty(n) for k in ("x", "y", "ur", "ut", "up", "w")}
+    out["id"] = np.empty(n, dtype=np.uint64)
+    if j0 != 0:
+        raise ValueError("j_range must start at 0")
+    # chunks of whole cells
+    per = max(pairs_per_cell, (chunk_pairs // max(pairs_per_cell, 1)) * max(pairs_per_cell, 1))
+    bounds = [(lo, min(lo + per, npair)) for lo in range(0, npair, per)]
+    if threads is None:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    args = [(out, lo, hi, p, pairs_per_cell, theta_T, weight, seed, k, i0, nj) for k, (lo, hi) in enumerate(bounds)]
+    if threads == 1 or len(args) == 1:
+        for a in args:
+            _pair_chunk(*a)
+    else:
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda a: _pair_chunk(*a), args))
+    return out
 
 
 def _rotator(nr, nth, bg, pairs_per_cell, steps, absorb_frac=0.1, inject=1, n_filt=3, seed=0,

@@ -1,0 +1,140 @@
+"""Helpers shared by the GPU parity tests: run the FP64 CPU oracle and the
+HIP library on the same seeded inputs and compare them.
+
+Tolerances (per step, from the precision of the arithmetic):
+  FP64 path: fields |a-b|_inf <= 1e-12 |b|_inf per component, offsets <= 1e-12
+             cells, momenta <= 1e-12 (|u| + 1e-3); cell indices identical
+             except where the oracle's coordinate lies within 1e-12 of a face.
+  FP32 path: the same with 1e-5 (2e-6 cells for the face band), the oracle
+             being fed the state rounded to the FP32 storage format.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle.oracle import Oracle
+
+TOL = {"fp64": dict(field=1e-12, off=1e-12, mom=1e-12, band=1e-12),
+       "fp32": dict(field=1e-5, off=1e-5, mom=1e-5, band=2e-6)}
+
+FIELD_COMPS = ["Er", "Eth", "Eph", "Br", "Bth", "Bph"]
+
+
+def round_to_storage(P: dict, precision: str, nth: int) -> dict:
+    """The particle state as the library stores it: int cell + in-cell
+    offset, offsets/momenta/weights rounded to FP32 for an FP32 context."""
+    if precision == "fp64":
+        return {k: np.array(v, copy=True) for k, v in P.items()}
+    Q = {}
+    x, y = P["x"], P["y"]
+    i = np.floor(x)
+    j = np.minimum(np.floor(y), nth - 1)
+    fx = (x - i).astype(np.float32)
+    fy = (y - j).astype(np.float32)
+    below = np.nextafter(np.float32(1), np.float32(0))
+    fx = np.where(fx >= 1, below, fx)
+    fy = np.where((fy >= 1) & (j < nth - 1), below, np.minimum(fy, np.float32(1)))
+    Q["x"] = i + fx.astype(np.float64)
+    Q["y"] = j + fy.astype(np.float64)
+    for k in ("ur", "ut", "up", "w"):
+        Q[k] = P[k].astype(np.float32).astype(np.float64)
+    Q["id"] = np.array(P["id"], copy=True)
+    return Q
+
+
+def make_pair(params: dict, P: dict | None, precision: str, capacity=None, fields=None, step_index=0,
+              carry=None, **simkw):
+    """An oracle and a GPU simulation holding the same state."""
+    from paper_1407_1810_amd.binding import Sim
+    nth = params["nth"]
+    o = Oracle(params)
+    n = 0 if P is None else len(P["x"])
+    cap = capacity if capacity is not None else max(4 * n + (1 << 16), 1 << 16)
+    s = Sim(params, precision=precision, capacity=cap, **simkw)
+    if P is not None and n:
+        R = round_to_storage(P, precision, nth)
+        o.add_particles(R["x"], R["y"], R["ur"], R["ut"], R["up"], R["w"], R["id"])
+        s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+    if fields:
+        for comp, a in fields.items():
+            a = np.asarray(a, dtype=np.float64)
+            if precision == "fp32":
+                a = a.astype(np.float32).astype(np.float64)
+            o.set_field(comp, a)
+            s.set_field(comp, a)
+    if step_index:
+        o.set_step_index(step_index)
+        s.set_step_index(step_index)
+    if carry is not None:
+        o.set_carry(carry)
+        s.set_carry(carry)
+    return o, s
+
+
+def rel_inf(a, b):
+    d = np.abs(a - b).max() if a.size else 0.0
+    sc = np.abs(b).max() if b.size else 0.0
+    return d / sc if sc > 0 else d
+
+
+def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=None):
+    worst = {}
+    for c in comps:
+        a, b = s.get_field(c), o.get_field(c)
+        assert a.shape == b.shape, (c, a.shape, b.shape)
+        e = rel_inf(a, b)
+        worst[c] = e
+        if report is not None:
+            report[c] = e
+        assert e <= tol, f"{c}: relative inf-norm error {e:.3e} > {tol:.1e}"
+    return worst
+
+
+def compare_particles(o, s, tol, nth, band, report=None):
+    Po, Ps = o.particles(), s.particles()
+    assert len(Po["x"]) == len(Ps["x"]), (len(Po["x"]), len(Ps["x"]))
+    ko, ks = np.argsort(Po["id"]), np.argsort(Ps["id"])
+    for k in Po:
+        Po[k] = Po[k][ko]
+        Ps[k] = Ps[k][ks]
+    assert np.array_equal(Po["id"], Ps["id"])
+    io, js = np.floor(Po["x"]), np.minimum(np.floor(Po["y"]), nth - 1)
+    ig, jg = np.floor(Ps["x"]), np.minimum(np.floor(Ps["y"]), nth - 1)
+    # distance of the oracle's coordinate to the nearest face
+    dx = np.abs(Po["x"] - np.round(Po["x"]))
+    dy = np.abs(Po["y"] - np.round(Po["y"]))
+    bad_i = (io != ig) & (dx > band)
+    bad_j = (js != jg) & (dy > band)
+    in_band = int(((io != ig) | (js != jg)).sum() - (bad_i | bad_j).sum())
+    assert not bad_i.any() and not bad_j.any(), f"{int(bad_i.sum() + bad_j.sum())} cell mismatches outside the band"
+    same = (io == ig) & (js == jg)
+    ex = np.abs(Po["x"] - Ps["x"])[same].max(initial=0.0)
+    ey = np.abs(Po["y"] - Ps["y"])[same].max(initial=0.0)
+    emom = 0.0
+    for k in ("ur", "ut", "up"):
+        e = (np.abs(Po[k] - Ps[k]) / (np.abs(Po[k]) + 1e-3)).max(initial=0.0)
+        emom = max(emom, e)
+    assert np.array_equal(Po["w"], Ps["w"]) or np.abs(Po["w"] - Ps["w"]).max() <= 1e-7 * np.abs(Po["w"]).max()
+    if report is not None:
+        report.update(off_x=ex, off_y=ey, mom=emom, in_band=in_band, n=len(Po["x"]))
+    assert ex <= tol["off"] and ey <= tol["off"], (ex, ey)
+    assert emom <= tol["mom"], emom
+    return dict(off_x=ex, off_y=ey, mom=emom, in_band=in_band)
+
+
+def random_fields(o, rng, scale=1e-3):
+    """Random E and B obeying the conducting-wall and axis conditions."""
+    out = {}
+    for comp in FIELD_COMPS:
+        r, k, _ = o.shape(comp)
+        a = rng.normal(size=(r, k)) * scale
+        if comp in ("Eth", "Eph", "Br"):
+            a[0, :] = 0
+            a[-1, :] = 0
+        if comp in ("Eph", "Bth"):
+            a[:, 0] = 0
+            a[:, -1] = 0
+        out[comp] = a
+    return out

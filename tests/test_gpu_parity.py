@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same
+seeded inputs, through the C ABI.  Every test here needs an MI355X."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1407_1810_amd import workloads as W
+from parity_util import (FIELD_COMPS, TOL, compare_fields, compare_particles, make_pair, random_fields,
+                         round_to_storage)
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp64", "fp32"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    from paper_1407_1810_amd.binding import gpu_available, lib
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    lib()
+
+
+def _small(**kw):
+    cfg = W.small_config(**kw)
+    P = W.pair_plasma(cfg["params"], cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
+    return cfg, P
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_fields_only_one_and_five_steps(prec):
+    """Field solver alone (random E, B satisfying the wall/axis conditions,
+    lossy layer on, no particles)."""
+    cfg = W.small_config(nr=37, nth=29, pairs_per_cell=0, absorb_cells=6)
+    p = cfg["params"]
+    from oracle.oracle import Oracle
+    rng = np.random.default_rng(1)
+    flds = random_fields(Oracle(p), rng)
+    _say("fields-only", prec)
+    o, s = make_pair(p, None, prec, fields=flds)
+    o.step(1)
+    s.step(1)
+    compare_fields(o, s, TOL[prec]["field"], comps=FIELD_COMPS)
+    o.step(4)
+    s.step(4)
+    compare_fields(o, s, 5 * TOL[prec]["field"], comps=FIELD_COMPS)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("nf", [0, 3])
+def test_one_step_with_particles(prec, nf):
+    """One full step from identical inputs: fields (E, B and the filtered
+    face charges) and every particle, matched by id."""
+    cfg, P = _small(nr=40, nth=36, pairs_per_cell=4, n_filt=nf, absorb_cells=5, theta_T=0.3)
+    p = cfg["params"]
+    # unpair half of the particles so that the plasma field is not zero
+    P["x"][1::4] = np.clip(P["x"][1::4] + 0.41, 0.0, p["nr"] - 1e-9)
+    _say("one-step", prec, nf, len(P["x"]))
+    from oracle.oracle import Oracle
+    flds = random_fields(Oracle(p), np.random.default_rng(2), scale=3e-3)
+    o, s = make_pair(p, P, prec, fields=flds)
+    o.step(1)
+    s.step(1)
+    t = TOL[prec]
+    compare_fields(o, s, t["field"])
+    compare_particles(o, s, t, p["nth"], t["band"])
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_lds_and_global_paths_and_sort(prec):
+    """Same result with the chunk staged in LDS (after a sort) and with the
+    global-memory path (no sort: chunks of scattered particles)."""
+    cfg, P = _small(nr=48, nth=40, pairs_per_cell=6, n_filt=2)
+    p = cfg["params"]
+    res = {}
+    for si in (1, -1):
+        o, s = make_pair(p, P, prec, sort_interval=si, tile=(4, 4))
+        o.step(3)
+        s.step(3)
+        t = dict(TOL[prec])
+        t = {k: v * 30 for k, v in t.items()}
+        compare_fields(o, s, t["field"])
+        compare_particles(o, s, t, p["nth"], t["band"])
+        res[si] = s.get_field("Er")
+    assert np.allclose(res[1], res[-1], rtol=0, atol=1e3 * TOL[prec]["field"] * np.abs(res[1]).max())
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_ten_steps_monopole_rotator_with_injection(prec):
+    """Ten steps of a small monopole rotator: spin-up, surface injection
+    (same pairs, same Philox positions), deletion, lossy layer."""
+    cfg = W.small_config(nr=32, nth=24, pairs_per_cell=2, n_filt=3, absorb_cells=5, bg="monopole",
+                         omega_frac=0.3, inject=1)
+    p = dict(cfg["params"], q_inj=cfg["params"]["q_inj"] * 0.05, t_spin=6.0)
+    P = W.pair_plasma(p, 2, 0.2, cfg["weight"], 3)
+    o, s = make_pair(p, P, prec)
+    t = TOL[prec]
+    for k in range(10):
+        o.step(1)
+        s.step(1)
+        _say("rotator step", k, "n", o.n)
+        scale = 1.0 if prec == "fp32" else (k + 1)
+        compare_fields(o, s, t["field"] * 20 * scale)
+        compare_particles(o, s, {kk: v * 20 * scale for kk, v in t.items()}, p["nth"], t["band"] * 20 * scale)
+    assert o.counters()[0] > 0
+    assert s.counts()["injected"] == o.counters()[0]
+    assert np.allclose(s.carry(), o.carry(), atol=1e-9 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_gauss_law_held_over_100_steps(prec):
+    """Charge conservation on the GPU: the Gauss residual (E flux minus the
+    filtered particle charge, in FP64) stays constant; FP64 at roundoff, FP32
+    at the FP32 storage roundoff of E."""
+    cfg, P = _small(nr=40, nth=32, pairs_per_cell=4, n_filt=3, absorb_cells=5, theta_T=0.3)
+    p = cfg["params"]
+    P["x"][1::2] = np.clip(P["x"][1::2] + 0.37, 0, p["nr"] - 1e-9)
+    from paper_1407_1810_amd.binding import Sim
+    s = Sim(p, precision=prec, capacity=len(P["x"]) + 10)
+    s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+    G0, Q0 = s.gauss()
+    s.step(100)
+    G, Q = s.gauss()
+    inner = slice(1, p["nr"] - p["absorb_cells"])
+    drift = np.abs((G - Q)[inner] - (G0 - Q0)[inner]).max()
+    scale = np.abs(Q[inner]).max()
+    _say("gauss drift", prec, drift, scale)
+    bound = 1e-12 if prec == "fp64" else 1e-5
+    assert drift <= bound * scale
+
+
+def test_edge_cases_poles_conductors_deletion():
+    """Particles exactly on the poles, on faces, inside both conductors,
+    moving out of the grid (deleted), and zero-weight test particles."""
+    cfg = W.small_config(nr=20, nth=16, pairs_per_cell=0, n_filt=2, absorb_cells=3, bg="monopole",
+                         omega_frac=0.2)
+    p = cfg["params"]
+    u = 0.95 / math.sqrt(1 - 0.95 ** 2)
+    x = np.array([5.0, 5.5, 7.0, 3.25, -2.5, -3.9, 21.5, 22.9, 0.0, 20.0, 10.0, 10.0])
+    y = np.array([0.0, 16.0, 8.0, 0.0, 4.0, 12.0, 3.0, 9.0, 8.0, 8.0, 1e-13, 16.0 - 1e-13])
+    ur = np.array([0.0, 0.1, u, -0.3, -u, -u, u, u, -0.2, 0.3, 0.0, 0.0])
+    ut = np.array([0.5, -0.5, 0.0, 0.2, 0.0, 0.0, 0.0, 0.0, 0.1, 0.0, -0.7, 0.7])
+    up = np.array([0.0, 0.2, 0.0, 0.1, 0.3, 0.0, 0.0, 0.0, 0.0, 0.1, 0.0, 0.0])
+    w = np.array([1, -1, 1, -1, 1, -1, 1, -1, 1e-30, -1e-30, 1, -1], dtype=float) * cfg["weight"]
+    P = dict(x=x, y=y, ur=ur, ut=ut, up=up, w=w, id=np.arange(len(x), dtype=np.uint64))
+    for prec in PRECISIONS:
+        o, s = make_pair(p, P, prec)
+        for k in range(6):
+            o.step(1)
+            s.step(1)
+            t = TOL[prec]
+            compare_fields(o, s, t["field"] * 10)
+            compare_particles(o, s, {kk: v * 10 for kk, v in t.items()}, p["nth"], t["band"] * 10)
+        assert o.counters()[1] >= 1  # something was deleted
+        assert s.counts()["deleted"] == o.counters()[1]
+
+
+def test_error_codes():
+    from paper_1407_1810_amd.binding import PicError, Sim
+    cfg = W.small_config(nr=16, nth=12, pairs_per_cell=0)
+    p = cfg["params"]
+    # capacity
+    s = Sim(p, precision="fp32", capacity=3)
+    with pytest.raises(PicError) as e:
+        s.add_particles(np.full(4, 3.5), np.full(4, 2.5), np.zeros(4), np.zeros(4), np.zeros(4), np.ones(4))
+    assert e.value.code == -4
+    # position outside the grid
+    with pytest.raises(PicError) as e:
+        s.add_particles([3.5], [-0.5], [0.0], [0.0], [0.0], [1.0])
+    assert e.value.code == -1
+    # CFL: a particle moving more than a cell per step (c > 1 cell per step)
+    q = dict(p, c=3.0)
+    s2 = Sim(q, precision="fp64", capacity=10)
+    s2.add_particles([5.5], [6.0], [50.0], [0.0], [0.0], [0.0])
+    with pytest.raises(PicError) as e:
+        s2.step(1)
+    assert e.value.code == -3
+    # invalid descriptor
+    with pytest.raises(PicError):
+        Sim(dict(p, nth=2), precision="fp64", capacity=10)
+    # empty step is fine
+    s3 = Sim(p, precision="fp64", capacity=10)
+    s3.step(3)
+    assert s3.counts()["live"] == 0
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_tm_mode_on_gpu(prec):
+    """The TM-mode field test of Sec. 4.1 run through the library: the same
+    L2 error as the oracle (FP64) and a converged solution."""
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    import test_oracle_pins as T
+    roots = T._du1_roots(4)
+    N = 48
+    r_in, r_out = roots[0], roots[3]
+    dxi = math.log(r_out / r_in) / N
+    c0 = 0.4 * min(r_in * (math.exp(dxi) - 1), r_in * 2.0 / N)
+    nsteps = int(math.ceil(1.25 / c0))
+    c = 1.25 / nsteps
+    p = dict(nr=N, nth=N, r_in=r_in, r_out=r_out, r_kind="log", th_kind="eqarea", c=c, n_filt=0,
+             absorb_cells=0, bg_kind="none")
+    from oracle.oracle import Oracle
+    o = Oracle(p)
+    rb = o.geometry(1)
+    yh = np.arange(N) + 0.5
+    sh = 2.0 / N * np.sqrt(yh * (N - yh))
+    b0 = -(T._u1(rb) / rb)[:, None] * sh[None, :] * math.cos(-0.5 * c)
+    o2, s = make_pair(p, None, prec, fields={"Bph": b0})
+    o2.step(nsteps)
+    s.step(nsteps)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    compare_fields(o2, s, tol, comps=FIELD_COMPS)
