@@ -348,13 +348,19 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     else r += fx * p.dr_lin;
     T k, s;
     if (p.th_kind == 0) {
-        const T y = (T)j + fy;
+        // sin theta = (2/nth) sqrt(y (nth - y)); both factors formed from the
+        // cell index and the offset so that neither cancels near a pole
+        const T ys = (T)j + fy, yn = (T)(nth - j) - fy;
         k = p.k_node[j] - fy * p.two_over_nth;
-        s = p.two_over_nth * sqrt(fmax(y * (p.nth_f - y), (T)0));
-    } else {
+        s = p.two_over_nth * sqrt(fmax(ys * yn, (T)0));
+    } else if (2 * j < nth) {
         const T th = ((T)j + fy) * p.pi_over_nth;
         s = sin(th);
         k = cos(th);
+    } else { // measure the angle from the south pole
+        const T th = ((T)(nth - j) - fy) * p.pi_over_nth;
+        s = sin(th);
+        k = -cos(th);
     }
     const T u0 = p.ur[idx], u1 = p.ut[idx], u2 = p.up[idx];
     // Cartesian frame at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = (0, 1, 0)
@@ -387,8 +393,8 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     else dY = atan2(Rn * k - zs * s, Rn * s + zs * k) / p.pi_over_nth;
     const T X1 = fx + dX;
     T Y1 = fy + dY;
-    if ((T)j + Y1 < (T)0) Y1 = -(T)j;                    // reflection at the poles: y' in [0, nth]
-    if ((T)j + Y1 > p.nth_f) Y1 = p.nth_f - (T)j;
+    if (Y1 < (T)(-j)) Y1 = (T)(-j);                      // reflection at the poles: y' in [0, nth]
+    if (Y1 > (T)(nth - j)) Y1 = (T)(nth - j);
     if (!(fabs(X1 - fx) < (T)1 && fabs(Y1 - fy) < (T)1)) { // CFL (or a non-finite value)
         atomicOr(p.status, 1);
         return;

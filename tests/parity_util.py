@@ -3,7 +3,8 @@ HIP library on the same seeded inputs and compare them.
 
 Tolerances (per step, from the precision of the arithmetic):
   FP64 path: fields |a-b|_inf <= 1e-12 |b|_inf per component, offsets <= 1e-12
-             cells, momenta <= 1e-12 (|u| + 1e-3); cell indices identical
+             cells, momenta |u_a - u_b| <= 1e-12 (|u_b| + 1e-3) with |.| the
+             vector norm; cell indices identical
              except where the oracle's coordinate lies within 1e-12 of a face.
   FP32 path: the same with 1e-5 (2e-6 cells for the face band), the oracle
              being fed the state rounded to the FP32 storage format.
@@ -88,6 +89,10 @@ def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=N
         worst[c] = e
         if report is not None:
             report[c] = e
+        if e > tol:
+            k = np.unravel_index(np.abs(a - b).argmax(), a.shape)
+            print(f"{c}: worst at row {k[0]} col {k[1]} gpu {a[k]:.9e} oracle {b[k]:.9e} max|oracle| "
+                  f"{np.abs(b).max():.3e}", flush=True)
         assert e <= tol, f"{c}: relative inf-norm error {e:.3e} > {tol:.1e}"
     return worst
 
@@ -112,13 +117,21 @@ def compare_particles(o, s, tol, nth, band, report=None):
     same = (io == ig) & (js == jg)
     ex = np.abs(Po["x"] - Ps["x"])[same].max(initial=0.0)
     ey = np.abs(Po["y"] - Ps["y"])[same].max(initial=0.0)
-    emom = 0.0
-    for k in ("ur", "ut", "up"):
-        e = (np.abs(Po[k] - Ps[k]) / (np.abs(Po[k]) + 1e-3)).max(initial=0.0)
-        emom = max(emom, e)
+    # momentum error relative to the momentum magnitude (the local basis
+    # components of a vector carry the vector's absolute rounding error)
+    umag = np.sqrt(Po["ur"] ** 2 + Po["ut"] ** 2 + Po["up"] ** 2)
+    du = np.sqrt(sum((Po[k] - Ps[k]) ** 2 for k in ("ur", "ut", "up")))
+    emom = (du / (umag + 1e-3)).max(initial=0.0)
     assert np.array_equal(Po["w"], Ps["w"]) or np.abs(Po["w"] - Ps["w"]).max() <= 1e-7 * np.abs(Po["w"]).max()
     if report is not None:
         report.update(off_x=ex, off_y=ey, mom=emom, in_band=in_band, n=len(Po["x"]))
+    if emom > tol["mom"] or ex > tol["off"] or ey > tol["off"]:
+        err = du / (umag + 1e-3) + np.abs(Po["x"] - Ps["x"]) + np.abs(Po["y"] - Ps["y"])
+        for q in np.argsort(err)[-6:]:
+            print(f"worst particle id {int(Po['id'][q])}: oracle x {Po['x'][q]:.9f} y {Po['y'][q]:.9f} "
+                  f"u ({Po['ur'][q]:.6e}, {Po['ut'][q]:.6e}, {Po['up'][q]:.6e}) w {Po['w'][q]:.3e} | gpu x "
+                  f"{Ps['x'][q]:.9f} y {Ps['y'][q]:.9f} u ({Ps['ur'][q]:.6e}, {Ps['ut'][q]:.6e}, {Ps['up'][q]:.6e})",
+                  flush=True)
     assert ex <= tol["off"] and ey <= tol["off"], (ex, ey)
     assert emom <= tol["mom"], emom
     return dict(off_x=ex, off_y=ey, mom=emom, in_band=in_band)
