@@ -36,12 +36,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval):
+def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt):
     from paper_1407_1810_amd.binding import Sim
     p = cfg["params"]
     n = len(P["x"])
     cap = n + 16 * (1 << 20)
-    s = Sim(p, precision=precision, capacity=cap, ids=False, tile=tile, sort_interval=sort_interval)
+    s = Sim(p, precision=precision, capacity=cap, ids=False, tile=tile, sort_interval=sort_interval, chunk_ppt=ppt)
     t0 = time.perf_counter()
     s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"])
     log(f"[{precision}] loaded {n} particles in {time.perf_counter() - t0:.1f} s")
@@ -105,9 +105,22 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=str, default="8x8")
-    ap.add_argument("--sort-interval", type=int, default=4)
+    ap.add_argument("--tile", type=str, default="4x8")
+    ap.add_argument("--sort-interval", type=int, default=8)
+    ap.add_argument("--ppt", type=int, default=8, help="particles per thread of a push work-group (4, 8, 16)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB three times")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is not sharded across "
               f"GPUs in this build", file=sys.stderr)
@@ -120,10 +133,10 @@ def main():
     n = len(P["x"])
     log(f"generated {n} particles for {cfg['name']} in {time.perf_counter() - t0:.1f} s")
     tile = tuple(int(v) for v in args.tile.split("x"))
-    r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, args.sort_interval)
+    r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, args.sort_interval, args.ppt)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, args.sort_interval)
+        r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, args.sort_interval, args.ppt)
     cells = p["nr"] * p["nth"]
     push_ms = r32["stage_ms"]["push"]
     bytes_launch = PUSH_BYTES["fp32"] * r32["mean_live"] + CELL_BYTES["fp32"] * cells
@@ -145,9 +158,10 @@ def main():
         "config": {"workload": cfg["name"], "grid": f"{p['nr']}x{p['nth']}", "particles": n,
                    "particles_per_cell": 2 * cfg["pairs_per_cell"], "background": p["bg_kind"],
                    "injection": bool(p["inject"]), "n_filt": p["n_filt"], "absorb_cells": p["absorb_cells"],
-                   "tile": args.tile, "sort_interval": args.sort_interval, "precision": "fp32"},
+                   "tile": args.tile, "sort_interval": args.sort_interval, "particles_per_thread": args.ppt,
+                   "precision": "fp32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push<float,4>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_push<float,{args.ppt}>",
                      "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_launch},
         "stage_ms": {k: round(v, 5) for k, v in r32["stage_ms"].items()},
         "fp64_gpu": None if r64 is None else {

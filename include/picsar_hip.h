@@ -92,6 +92,7 @@ typedef struct {
     int32_t tile_r, tile_th;  /* sort tile in cells (0 = 8 x 8) */
     int32_t sort_interval;    /* steps between sorts (0 = 4; < 0 = never) */
     int32_t flags;            /* PIC_FLAG_* */
+    int32_t chunk_ppt;        /* particles per thread of a push work-group: 4, 8, 16 (0 = 8) */
 } pic_grid_desc;
 
 /* Analytic initial fields and injection (Sec. 5.2, 5.3, 4.3). */

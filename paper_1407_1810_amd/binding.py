@@ -42,7 +42,8 @@ class GridDesc(C.Structure):
                 ("r_kind", C.c_int32), ("th_kind", C.c_int32), ("c", C.c_double), ("n_filt", C.c_int32),
                 ("absorb_cells", C.c_int32), ("sigma_max", C.c_double), ("precision", C.c_int32),
                 ("mover", C.c_int32), ("particle_capacity", C.c_int64), ("tile_r", C.c_int32),
-                ("tile_th", C.c_int32), ("sort_interval", C.c_int32), ("flags", C.c_int32)]
+                ("tile_th", C.c_int32), ("sort_interval", C.c_int32), ("flags", C.c_int32),
+                ("chunk_ppt", C.c_int32)]
 
 
 class PhysDesc(C.Structure):
@@ -98,7 +99,7 @@ class Sim:
     numerics and analytic-field keys, see workloads.py)."""
 
     def __init__(self, params: dict, precision: str = "fp64", capacity: int = 1 << 20, device: int = 0,
-                 tile=(0, 0), sort_interval: int = 0, ids: bool = True, stream=None):
+                 tile=(0, 0), sort_interval: int = 0, ids: bool = True, stream=None, chunk_ppt: int = 0):
         L = lib()
         self._h = C.c_void_p()
         rc = L.pic_create(C.byref(self._h), int(device), stream)
@@ -119,6 +120,7 @@ class Sim:
         g.tile_r, g.tile_th = int(tile[0]), int(tile[1])
         g.sort_interval = int(sort_interval)
         g.flags = FLAG_IDS if ids else 0
+        g.chunk_ppt = int(chunk_ppt)
         ph = PhysDesc()
         ph.bg_kind = BG_KIND[params.get("bg_kind", "none")]
         ph.B0 = float(params.get("B0", 0.0))

@@ -91,13 +91,73 @@ __device__ inline void add_background(const Background &bg, T inv_rl, bool insid
 }
 
 // ---------------------------------------------------------------------
+// Math policy.  FP32: hardware reciprocal, reciprocal square root and
+// square root (1 ulp), exp via v_exp_f32, and short series for the small
+// arguments the push sees (log1p of r'/r - 1, atan of the azimuthal step),
+// falling back to the library outside their range; all far inside the FP32
+// parity tolerance.  FP64: IEEE division / square root and the library
+// functions, for parity at 1e-12 with the FP64 oracle.
+// ---------------------------------------------------------------------
+template <typename T>
+struct FM;
+
+template <>
+struct FM<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    // log(1 + e): alternating series through e^8 for |e| < 1/32 (truncation < e^9 / 9)
+    static __device__ __forceinline__ float log1p(float e)
+    {
+        if (fabsf(e) < 0.03125f) {
+            const float p = 1.0f / 7 - e * (1.0f / 8);
+            float v = 1.0f / 6 - e * p;
+            v = 1.0f / 5 - e * v;
+            v = 0.25f - e * (v);
+            v = 1.0f / 3 - e * v;
+            v = 0.5f - e * v;
+            return e - e * e * v;
+        }
+        return log1pf(e);
+    }
+    // atan2(y, x) for x > 0 and |y| < x / 4: odd series of atan(y / x)
+    // through t^13 (truncation < t^15 / 15 < 1e-10), else the library
+    static __device__ __forceinline__ float atan2(float y, float x)
+    {
+        if (x > 0.f && fabsf(y) < 0.25f * x) {
+            const float t = y * __builtin_amdgcn_rcpf(x), t2 = t * t;
+            float v = 1.0f / 11 - t2 * (1.0f / 13);
+            v = 1.0f / 9 - t2 * v;
+            v = 1.0f / 7 - t2 * v;
+            v = 0.2f - t2 * v;
+            v = 1.0f / 3 - t2 * v;
+            return t - t * t2 * v;
+        }
+        return atan2f(y, x);
+    }
+};
+
+template <>
+struct FM<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double log1p(double e) { return ::log1p(e); }
+    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+};
+
+// ---------------------------------------------------------------------
 // Movers (Cartesian).  u = gamma v / c, eps = q dt / (2 m c).
 // ---------------------------------------------------------------------
 
 template <typename T>
 __device__ inline void vay_push(T u[3], const T E[3], const T B[3], T eps)
 {
-    const T ig = (T)1 / sqrt((T)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const T ig = FM<T>::rsqrt((T)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const T vx = u[0] * ig, vy = u[1] * ig, vz = u[2] * ig;
     // half electric kick twice and the magnetic rotation with the old velocity
     const T px = u[0] + (T)2 * eps * E[0] + eps * (vy * B[2] - vz * B[1]);
@@ -107,10 +167,10 @@ __device__ inline void vay_push(T u[3], const T E[3], const T B[3], T eps)
     const T tau2 = tx * tx + ty * ty + tz * tz;
     const T us = px * tx + py * ty + pz * tz;
     const T sg = (T)1 + px * px + py * py + pz * pz - tau2;
-    const T g2 = (T)0.5 * (sg + sqrt(sg * sg + (T)4 * (tau2 + us * us)));
-    const T ign = (T)1 / sqrt(g2);
+    const T g2 = (T)0.5 * (sg + FM<T>::sqrt(sg * sg + (T)4 * (tau2 + us * us)));
+    const T ign = FM<T>::rsqrt(g2);
     const T ax = tx * ign, ay = ty * ign, az = tz * ign;
-    const T sf = (T)1 / ((T)1 + ax * ax + ay * ay + az * az);
+    const T sf = FM<T>::rcp((T)1 + ax * ax + ay * ay + az * az);
     const T pt = px * ax + py * ay + pz * az;
     u[0] = sf * (px + pt * ax + (py * az - pz * ay));
     u[1] = sf * (py + pt * ay + (pz * ax - px * az));
@@ -121,9 +181,9 @@ template <typename T>
 __device__ inline void boris_push(T u[3], const T E[3], const T B[3], T eps)
 {
     const T mx = u[0] + eps * E[0], my = u[1] + eps * E[1], mz = u[2] + eps * E[2];
-    const T ig = (T)1 / sqrt((T)1 + mx * mx + my * my + mz * mz);
+    const T ig = FM<T>::rsqrt((T)1 + mx * mx + my * my + mz * mz);
     const T tx = eps * B[0] * ig, ty = eps * B[1] * ig, tz = eps * B[2] * ig;
-    const T f = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
+    const T f = (T)2 * FM<T>::rcp((T)1 + tx * tx + ty * ty + tz * tz);
     const T qx = mx + (my * tz - mz * ty), qy = my + (mz * tx - mx * tz), qz = mz + (mx * ty - my * tx);
     u[0] = mx + f * (qy * tz - qz * ty) + eps * E[0];
     u[1] = my + f * (qz * tx - qx * tz) + eps * E[1];

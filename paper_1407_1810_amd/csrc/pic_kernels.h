@@ -184,7 +184,7 @@ struct PushArgs {
     Fields<T> f;          // E, B (read) and F (deposit target)
     Background bg;
     int r_kind, th_kind, mover, n_filt;
-    T c, dxi, dr_lin, nth_f, two_over_nth, pi_over_nth, eps0, inv_rl;
+    T c, dxi, inv_dxi, nth_f, two_over_nth, pi_over_nth, inv_pi_over_nth, eps0, inv_rl;
     const T *r_node;      // r(i) at [i + G]
     const T *k_node;      // cos theta_j
     uint32_t *cell;
@@ -193,7 +193,9 @@ struct PushArgs {
     const unsigned long long *n_total;
     unsigned long long *n_dead;
     int *status;
+    unsigned int *work;   // 8 chunk counters (one per XCD), zero at launch
     int lds_cap;          // entries per LDS plane, 0 = gather/deposit in global memory
+    T dep_scale, dep_inv; // fixed-point scale of the LDS deposit planes and its inverse
 };
 
 template <typename T>
@@ -225,11 +227,27 @@ struct LdsView {
     __device__ T geth(int c, int i, int j, T) const { return get(c, i, j); } // mirror staged
 };
 
+// Deposit planes in LDS hold 64-bit fixed point: a contribution v is stored
+// as round(v * scale) with scale = 2^48 / max|w|, so integer LDS atomics
+// (much faster than floating-point ones) accumulate it exactly; a chunk of
+// at most 4096 particles, each adding at most four contributions of at most
+// max|w| to an entry, stays below 2^62.
+template <typename T>
+__device__ __forceinline__ long long to_fixed(T v, T scale);
+template <>
+__device__ __forceinline__ long long to_fixed<float>(float v, float scale) { return __float2ll_rn(v * scale); }
+template <>
+__device__ __forceinline__ long long to_fixed<double>(double v, double scale) { return __double2ll_rn(v * scale); }
+
 template <typename T>
 struct LdsDep {
-    T *s;
+    long long *s;
     int cap, i0, j0, C;
-    __device__ void add(int c, int i, int j, T v) const { atomicAdd(&s[c * cap + (i - i0) * C + (j - j0)], v); }
+    T scale;
+    __device__ void add(int c, int i, int j, T v) const
+    {
+        atomicAdd((unsigned long long *)&s[c * cap + (i - i0) * C + (j - j0)], (unsigned long long)to_fixed(v, scale));
+    }
 };
 
 template <typename T>
@@ -290,7 +308,7 @@ __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0,
     int np = 0;
     px[np] = x0; py[np] = y0; ++np;
     if (cx && cy) {
-        const T tx = (X - x0) / (x1 - x0), ty = (Y - y0) / (y1 - y0);
+        const T tx = FM<T>::div(X - x0, x1 - x0), ty = FM<T>::div(Y - y0, y1 - y0);
         if (tx < ty) {
             px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
             px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
@@ -301,10 +319,10 @@ __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0,
             px[np] = X; py[np] = Y; ++np;
         }
     } else if (cx) {
-        const T tx = (X - x0) / (x1 - x0);
+        const T tx = FM<T>::div(X - x0, x1 - x0);
         px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
     } else if (cy) {
-        const T ty = (Y - y0) / (y1 - y0);
+        const T ty = FM<T>::div(Y - y0, y1 - y0);
         px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
     }
     px[np] = x1; py[np] = y1; ++np;
@@ -344,15 +362,15 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     const T fx = p.dx[idx], fy = p.dy[idx];
     const T w = p.w[idx];
     T r = p.r_node[i + p.L.G];
-    if (p.r_kind == 0) r *= exp(fx * p.dxi);
-    else r += fx * p.dr_lin;
+    if (p.r_kind == 0) r *= FM<T>::exp(fx * p.dxi);
+    else r += fx * p.dxi;
     T k, s;
     if (p.th_kind == 0) {
         // sin theta = (2/nth) sqrt(y (nth - y)); both factors formed from the
         // cell index and the offset so that neither cancels near a pole
         const T ys = (T)j + fy, yn = (T)(nth - j) - fy;
         k = p.k_node[j] - fy * p.two_over_nth;
-        s = p.two_over_nth * sqrt(fmax(ys * yn, (T)0));
+        s = p.two_over_nth * FM<T>::sqrt(fmax(ys * yn, (T)0));
     } else if (2 * j < nth) {
         const T th = ((T)j + fy) * p.pi_over_nth;
         s = sin(th);
@@ -378,19 +396,19 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
         else boris_push(uc, Ec, Bc, eps);
     }
     // displacement over the step, relative to r
-    const T vg = p.c / sqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
-    const T ir = (T)1 / r;
+    const T vg = p.c * FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+    const T ir = FM<T>::rcp(r);
     const T ex = uc[0] * vg * ir, ey = uc[1] * vg * ir, ez = uc[2] * vg * ir;
     const T xs = s + ex, zs = k + ez;                    // (R', Z') / r
     const T q = (T)2 * (s * ex + k * ez) + ex * ex + ey * ey + ez * ez;
-    const T sq = sqrt((T)1 + q);                         // r' / r
-    const T eta = q / ((T)1 + sq);                       // r' / r - 1
-    const T dX = p.r_kind == 0 ? log1p(eta) / p.dxi : r * eta / p.dr_lin;
-    const T Rn = sqrt(xs * xs + ey * ey);
-    const T isq = (T)1 / sq;
+    const T sq = FM<T>::sqrt((T)1 + q);                  // r' / r
+    const T eta = FM<T>::div(q, (T)1 + sq);              // r' / r - 1
+    const T dX = p.r_kind == 0 ? FM<T>::log1p(eta) * p.inv_dxi : r * eta * p.inv_dxi;
+    const T Rn = FM<T>::sqrt(xs * xs + ey * ey);
+    const T isq = FM<T>::rcp(sq);
     T dY;
     if (p.th_kind == 0) dY = (T)-0.5 * p.nth_f * ((ez - k * eta) * isq);
-    else dY = atan2(Rn * k - zs * s, Rn * s + zs * k) / p.pi_over_nth;
+    else dY = FM<T>::atan2(Rn * k - zs * s, Rn * s + zs * k) * p.inv_pi_over_nth;
     const T X1 = fx + dX;
     T Y1 = fy + dY;
     if (Y1 < (T)(-j)) Y1 = (T)(-j);                      // reflection at the poles: y' in [0, nth]
@@ -400,8 +418,12 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
         return;
     }
     T cph = (T)1, sph = (T)0;
-    if (Rn > (T)0) { cph = xs / Rn; sph = ey / Rn; }
-    vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w, atan2(sph, cph));
+    if (Rn > (T)0) {
+        const T iR = FM<T>::rcp(Rn);
+        cph = xs * iR;
+        sph = ey * iR;
+    }
+    vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w, FM<T>::atan2(sph, cph));
     const T k1 = zs * isq, s1 = Rn * isq;
     const T ux = cph * uc[0] + sph * uc[1], uy = -sph * uc[0] + cph * uc[1], uz = uc[2];
     int ni = i, nj = j;
@@ -436,35 +458,68 @@ __device__ inline int wave_max(int v)
     return v;
 }
 
+// LDS of a push work-group: six field planes of T, then three 64-bit
+// fixed-point deposit planes (8-byte aligned).
+template <typename T>
+__host__ __device__ constexpr size_t lds_field_bytes(int cap)
+{
+    return ((size_t)6 * cap * sizeof(T) + 7) / 8 * 8;
+}
+template <typename T>
+__host__ __device__ constexpr size_t lds_push_bytes(int cap)
+{
+    return lds_field_bytes<T>(cap) + (size_t)3 * cap * sizeof(long long);
+}
+
+// Slot of iteration q of thread t inside a chunk: each pass of the 256
+// threads reads every other particle of a 512-particle block (even ones,
+// then odd ones), so the two members of a co-located pair -- stored next to
+// each other -- never deposit in the same LDS atomic instruction.
+__device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
+{
+    return base + 512 * (size_t)(q >> 1) + 2 * tid + (q & 1);
+}
+
 // One work-group per chunk of 256 * PPT consecutive (cell-sorted) particles.
 // The chunk's cell bounding box, widened by one cell below and two above
 // (gather stencils and one-cell moves), is staged in LDS when it fits:
 // six field planes with the axis mirror applied, and three face-charge
 // planes that collect the chunk's deposits with LDS atomics and are flushed
 // with one global atomic per non-zero entry.  Chunks that do not fit (an
-// unsorted tail) gather and deposit in global memory.  Work-group b serves
-// the chunk range of XCD b % 8 so that neighbouring chunks share an L2.
+// unsorted tail) gather and deposit in global memory.  The particle array is
+// cut into eight contiguous chunk ranges, one per XCD, so that neighbouring
+// chunks share an L2; work-group b takes chunks of range b % 8 from that
+// range's atomic counter until the range is exhausted, so late-starting
+// work-groups never leave a tail of unbalanced work.
 template <typename T, int PPT>
 __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
 {
+    static_assert(PPT % 2 == 0, "chunks are read in even/odd passes");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
+    T *sm = reinterpret_cast<T *>(smem_raw);                              // 6 field planes
+    long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>(p.lds_cap)); // 3 deposit planes
     __shared__ int red[4][4];
+    __shared__ unsigned int s_next;
     constexpr int CH = 256 * PPT;
     const unsigned long long n = *p.n_total;
     const long long nch = (long long)((n + CH - 1) / CH);
-    const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
     const long long lo = nch * xcd / 8, hi = nch * (xcd + 1) / 8;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cap = p.lds_cap;
     const int nth = p.L.nth;
-    for (long long ch = lo + loc; ch < hi; ch += nloc) {
+    for (;;) {
+        if (tid == 0) s_next = atomicAdd(&p.work[xcd], 1u);
+        __syncthreads();
+        const long long ch = lo + (long long)s_next;
+        __syncthreads();
+        if (ch >= hi) break;
         const size_t base = (size_t)ch * CH;
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = base + tid + 256 * q;
+                const size_t idx = chunk_slot(base, tid, q);
                 const uint32_t c = idx < n ? p.cell[idx] : kDead;
                 if (c != kDead) {
                     const int ci = cell_i(c), cj = cell_j(c);
@@ -495,8 +550,10 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
         }
         if (use) {
             const int RC = (imax - imin + 4) * C;
+            // walk the region row-major with (row, column) carried along
+            int rr = tid / C, cc = tid - (tid / C) * C;
+            const int dr = 256 / C, dc = 256 - (256 / C) * C;
             for (int e = tid; e < RC; e += 256) {
-                const int rr = e / C, cc = e - rr * C;
                 const int gi = i0 + rr, gj = j0 + cc;
                 const bool vi = gj >= 0 && gj <= nth;
                 int hj = gj;
@@ -510,26 +567,35 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
                 sm[cETH * cap + e] = vh ? so * p.f.c[cETH][p.L.at(gi, hj)] : (T)0;
                 sm[cBR * cap + e] = vh ? p.f.c[cBR][p.L.at(gi, hj)] : (T)0;
                 sm[cBPH * cap + e] = vh ? so * p.f.c[cBPH][p.L.at(gi, hj)] : (T)0;
-                sm[6 * cap + e] = (T)0;
-                sm[7 * cap + e] = (T)0;
-                sm[8 * cap + e] = (T)0;
+                sd[e] = 0;
+                sd[cap + e] = 0;
+                sd[2 * cap + e] = 0;
+                rr += dr;
+                cc += dc;
+                if (cc >= C) { cc -= C; ++rr; }
             }
             __syncthreads();
             const LdsView<T> view{sm, cap, i0, j0, C};
-            const LdsDep<T> dep{sm + 6 * cap, cap, i0, j0, C};
+            const LdsDep<T> dep{sd, cap, i0, j0, C, p.dep_scale};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = base + tid + 256 * q;
+                const size_t idx = chunk_slot(base, tid, q);
                 const uint32_t c = idx < n ? p.cell[idx] : kDead;
                 if (c != kDead) push_particle(p, view, dep, idx, c);
             }
             __syncthreads();
-            for (int e = tid; e < 3 * RC; e += 256) {
-                const int comp = e / RC, ee = e - comp * RC;
-                const T v = sm[(6 + comp) * cap + ee];
-                if (v != (T)0) {
-                    const int rr = ee / C, cc = ee - rr * C;
-                    unsafeAtomicAdd(&p.f.c[cFR + comp][p.L.at(i0 + rr, j0 + cc)], v);
+            {
+                int fr = tid / C, fc = tid - (tid / C) * C;
+                for (int e = tid; e < RC; e += 256) {
+                    const size_t g = p.L.at(i0 + fr, j0 + fc);
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) {
+                        const long long v = sd[comp * cap + e];
+                        if (v != 0) unsafeAtomicAdd(&p.f.c[cFR + comp][g], (T)v * p.dep_inv);
+                    }
+                    fr += dr;
+                    fc += dc;
+                    if (fc >= C) { fc -= C; ++fr; }
                 }
             }
             __syncthreads();
@@ -538,7 +604,7 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = base + tid + 256 * q;
+                const size_t idx = chunk_slot(base, tid, q);
                 const uint32_t c = idx < n ? p.cell[idx] : kDead;
                 if (c != kDead) push_particle(p, view, dep, idx, c);
             }
@@ -663,24 +729,53 @@ __device__ inline unsigned long long lanemask_le(int lane)
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
 
-// Histogram of tile keys; runs of equal keys inside a wave (the common case
-// for particles sorted a few steps ago) cost one atomic per run.
+// Particles per wave of the sort kernels: each wave walks a contiguous span
+// so that the particles of one tile (kept together by the previous sort) are
+// counted and placed by about one wave, not by dozens contending for the
+// same counter.
+constexpr int kSortSpan = 64 * 64;
+
+// Histogram of tile keys.  Within a span the last run of each 64-particle
+// window is kept pending and extended by the next window while the key
+// stays the same; a counter is touched only when a run ends.
 __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *__restrict__ cell,
                                                    const unsigned long long *n_total, TileMap tm,
                                                    unsigned int *__restrict__ counts)
 {
     const unsigned long long n = *n_total;
     const int lane = threadIdx.x & 63;
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long b = blockIdx.x * (unsigned long long)blockDim.x; b < n; b += stride) {
-        const unsigned long long idx = b + threadIdx.x;
-        const int key = idx < n ? tm.key(cell[idx]) : INT_MAX;
-        const int prev = __shfl_up(key, 1);
-        const bool head = lane == 0 || key != prev;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long after = heads & ~lanemask_le(lane);
-        const int next = after ? __ffsll((long long)after) - 1 : 64;
-        if (head && key != INT_MAX) atomicAdd(&counts[key], (unsigned int)(next - lane));
+    const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
+    const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
+    for (unsigned long long s0 = wave * kSortSpan; s0 < n; s0 += nwaves * kSortSpan) {
+        const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
+        int pend_key = -1;          // wave-uniform pending run
+        unsigned int pend_len = 0;
+        for (unsigned long long b = s0; b < s1; b += 64) {
+            const unsigned long long idx = b + lane;
+            const int key = idx < s1 ? tm.key(cell[idx]) : INT_MAX;
+            const int prev = __shfl_up(key, 1);
+            const bool head = lane == 0 || key != prev;
+            const unsigned long long heads = __ballot(head);
+            const unsigned long long after = heads & ~lanemask_le(lane);
+            const int next = after ? __ffsll((long long)after) - 1 : 64;
+            const int nruns = __popcll(heads);
+            const int first_key = __shfl(key, 0);
+            const int first_len = nruns > 1 ? __ffsll((long long)(heads & ~1ull)) - 1 : 64;
+            const int last_lane = 63 - __clzll((long long)heads);
+            const int last_key = __shfl(key, last_lane);
+            const bool extend = pend_key == first_key;
+            if (extend) pend_len += (unsigned int)first_len;
+            if (pend_key >= 0 && (!extend || nruns > 1)) { // the pending run has ended
+                if (lane == 0 && pend_key != INT_MAX) atomicAdd(&counts[pend_key], pend_len);
+            }
+            const bool complete = head && lane != last_lane && !(lane == 0 && extend);
+            if (complete && key != INT_MAX) atomicAdd(&counts[key], (unsigned int)(next - lane));
+            if (!(extend && nruns == 1)) {
+                pend_key = last_key;
+                pend_len = (unsigned int)(64 - last_lane);
+            }
+        }
+        if (lane == 0 && pend_key >= 0 && pend_key != INT_MAX) atomicAdd(&counts[pend_key], pend_len);
     }
 }
 
@@ -742,6 +837,8 @@ struct SortArgs {
     const unsigned long long *offsets;
     unsigned int *cursor;
     TileMap tm;
+    unsigned long long capacity;
+    int *status;
 };
 
 template <typename T>
@@ -749,27 +846,32 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs<T> s)
 {
     const unsigned long long n = *s.n_total;
     const int lane = threadIdx.x & 63;
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long b = blockIdx.x * (unsigned long long)blockDim.x; b < n; b += stride) {
-        const unsigned long long idx = b + threadIdx.x;
-        const uint32_t c = idx < n ? s.cell[idx] : kDead;
-        const int key = idx < n ? s.tm.key(c) : INT_MAX;
-        const int prev = __shfl_up(key, 1);
-        const bool head = lane == 0 || key != prev;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long after = heads & ~lanemask_le(lane);
-        const int next = after ? __ffsll((long long)after) - 1 : 64;
-        const bool live = key != INT_MAX && key != s.tm.n_keys;
-        unsigned int got = 0;
-        if (head && live) got = atomicAdd(&s.cursor[key], (unsigned int)(next - lane));
-        const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
-        got = __shfl(got, hl);
-        if (live) {
-            const unsigned long long d = s.offsets[key] + got + (lane - hl);
-            s.cell_o[d] = c;
+    const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
+    const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
+    for (unsigned long long s0 = wave * kSortSpan; s0 < n; s0 += nwaves * kSortSpan) {
+        const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
+        for (unsigned long long b = s0; b < s1; b += 64) {
+            const unsigned long long idx = b + lane;
+            const uint32_t c = idx < s1 ? s.cell[idx] : kDead;
+            const int key = idx < s1 ? s.tm.key(c) : INT_MAX;
+            const int prev = __shfl_up(key, 1);
+            const bool head = lane == 0 || key != prev;
+            const unsigned long long heads = __ballot(head);
+            const unsigned long long after = heads & ~lanemask_le(lane);
+            const int next = after ? __ffsll((long long)after) - 1 : 64;
+            const bool live = key != INT_MAX && key != s.tm.n_keys;
+            unsigned int got = 0;
+            if (head && live) got = atomicAdd(&s.cursor[key], (unsigned int)(next - lane));
+            const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
+            got = __shfl(got, hl);
+            const unsigned long long d = live ? s.offsets[key] + got + (lane - hl) : 0;
+            if (live && d >= s.capacity) atomicOr(s.status, 4); // never write outside the store
+            if (live && d < s.capacity) {
+                s.cell_o[d] = c;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) s.a_o[q][d] = s.a[q][idx];
-            if (s.id) s.id_o[d] = s.id[idx];
+                for (int q = 0; q < 6; ++q) s.a_o[q][d] = s.a[q][idx];
+                if (s.id) s.id_o[d] = s.id[idx];
+            }
         }
     }
 }

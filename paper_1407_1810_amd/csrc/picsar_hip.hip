@@ -131,6 +131,7 @@ public:
         tile_th_ = gd.tile_th > 0 ? gd.tile_th : 8;
         sort_interval_ = gd.sort_interval == 0 ? 4 : gd.sort_interval;
         cap_ = gd.particle_capacity;
+        if (ph.inject) qmax_ = std::fabs(ph.q_inj);
         with_ids_ = (gd.flags & PIC_FLAG_IDS) != 0;
 
         const size_t fsz = L.size();
@@ -152,6 +153,7 @@ public:
         fill(ctr_, 8, 0ull);
         status_ = dalloc<int>(1);
         fill(status_, 1, 0);
+        work_ = dalloc<unsigned int>(8);
         carry_ = dalloc<double>(nth + 1);
         fill(carry_, (size_t)nth + 1, 0.0);
         // sort tiles over rows -G..nr+G
@@ -161,12 +163,17 @@ public:
         counts_ = dalloc<unsigned int>(n_keys_ + 1);
         cursor_ = dalloc<unsigned int>(n_keys_ + 1);
         offsets_ = dalloc<unsigned long long>(n_keys_ + 1);
-        // LDS plane size: a tile plus the drift of sort_interval steps plus the stencil halo
-        const int drift = sort_interval_ > 0 ? sort_interval_ : 64;
-        const int R = tile_r_ + 2 * drift + 4, C = tile_th_ * 2 + 2 * drift + 4;
-        lds_cap_ = std::min(R * C, kMaxLdsBytes / (9 * (int)sizeof(T)));
-        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, kPPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   9 * lds_cap_ * (int)sizeof(T)));
+        // LDS plane size: a chunk spans at most two neighbouring tiles (serpentine
+        // order), widened by the drift since the last sort (at most ~0.7 cell
+        // per step in grid units) and the stencil halo (one cell below, two above)
+        ppt_ = gd.chunk_ppt > 0 ? gd.chunk_ppt : 8;
+        const int drift = sort_interval_ > 0 ? (7 * sort_interval_ + 9) / 10 : 0;
+        const int R = 2 * tile_r_ + 2 * drift + 3, C = 2 * tile_th_ + 2 * drift + 3;
+        lds_cap_ = sort_interval_ > 0 ? std::min(R * C, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
+        const int shm = (int)lds_push_bytes<T>(std::max(lds_cap_, 1));
+        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
         HIPCHK(hipStreamSynchronize(stream));
     }
 
@@ -184,6 +191,7 @@ public:
         HIPCHK(hipMemcpyAsync(&ntot, ctr_ + kTotal, sizeof ntot, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         if ((int64_t)ntot + n > cap_) throw StatusError{PIC_ECAPACITY, "particle capacity exceeded"};
+        for (int64_t q = 0; q < n; ++q) qmax_ = std::max(qmax_, std::fabs(w[q]));
         const int64_t chunk = 1 << 22;
         double *stage = dalloc_tmp<double>(6 * (size_t)std::min(n, chunk));
         uint64_t *sid = id ? dalloc_tmp<uint64_t>((size_t)std::min(n, chunk)) : nullptr;
@@ -253,6 +261,10 @@ public:
         if (st & 2) {
             fill(status_, 1, 0);
             throw StatusError{PIC_ECAPACITY, "particle capacity exceeded by surface injection"};
+        }
+        if (st & 4) {
+            fill(status_, 1, 0);
+            throw StatusError{PIC_EDEVICE, "internal error: sort destination outside the particle store"};
         }
     }
 
@@ -383,7 +395,7 @@ public:
     void stage_ms(double *out) override { std::memcpy(out, stage_ms_, sizeof stage_ms_); }
 
 private:
-    static constexpr int kPPT = 4;
+    int ppt_ = 8;
     static constexpr int kMaxLdsBytes = 64 * 1024;
     enum { kTotal = 0, kDeadSinceSort = 1, kDeleted = 2, kInjected = 3, kLive = 4, kPartSteps = 5 };
 
@@ -397,6 +409,7 @@ private:
     int cur_ = 0;
     unsigned long long *ctr_ = nullptr;
     int *status_ = nullptr;
+    unsigned int *work_ = nullptr;
     double *carry_ = nullptr;
     unsigned int *counts_ = nullptr, *cursor_ = nullptr;
     unsigned long long *offsets_ = nullptr;
@@ -404,6 +417,7 @@ private:
     int tile_r_ = 8, tile_th_ = 8, sort_interval_ = 4;
     int lds_cap_ = 0;
     int64_t cap_ = 0, n_bound_ = 0;
+    double qmax_ = 0.0; // largest |w| held so far: sets the fixed-point deposit scale
     bool with_ids_ = false, need_sort_ = true;
     Metric<T> m_{};
     const T *r_node_ = nullptr, *k_node_ = nullptr;
@@ -582,7 +596,9 @@ private:
         TileMap tm{L.G, tile_r_, tile_th_, ntj_, n_keys_};
         fill(counts_, (size_t)n_keys_ + 1, 0u);
         fill(cursor_, (size_t)n_keys_ + 1, 0u);
-        const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n_bound_ + 255) / 256, 1), 8192);
+        // one wave per span of kSortSpan particles (4 waves per block)
+        const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n_bound_ + 4 * kSortSpan - 1) / (4 * kSortSpan), 1),
+                                                  8192);
         k_sort_hist<<<blocks, 256, 0, stream>>>(cell_[cur_], ctr_ + kTotal, tm, counts_);
         HIPCHK(hipGetLastError());
         k_sort_scan<<<1, 1024, 0, stream>>>(counts_, n_keys_, offsets_, ctr_ + kTotal, ctr_ + kLive);
@@ -601,6 +617,8 @@ private:
         sa.offsets = offsets_;
         sa.cursor = cursor_;
         sa.tm = tm;
+        sa.capacity = (unsigned long long)cap_;
+        sa.status = status_;
         k_sort_scatter<T><<<blocks, 256, 0, stream>>>(sa);
         HIPCHK(hipGetLastError());
         k_finish_sort<<<1, 1, 0, stream>>>(ctr_);
@@ -720,10 +738,11 @@ private:
         p.n_filt = gd.n_filt;
         p.c = (T)gd.c;
         p.dxi = (T)geo.dxi;
-        p.dr_lin = (T)geo.dxi;
+        p.inv_dxi = (T)(1.0 / geo.dxi);
         p.nth_f = (T)gd.nth;
         p.two_over_nth = (T)(2.0 / gd.nth);
         p.pi_over_nth = (T)(kPi / gd.nth);
+        p.inv_pi_over_nth = (T)(gd.nth / kPi);
         p.eps0 = (T)(ph.q_over_m / (2.0 * gd.c));
         p.inv_rl = (T)irl;
         p.r_node = r_node_;
@@ -738,12 +757,19 @@ private:
         p.n_total = ctr_ + kTotal;
         p.n_dead = ctr_ + kDeadSinceSort;
         p.status = status_;
+        p.work = work_;
         p.lds_cap = use_lds_ ? lds_cap_ : 0;
-        constexpr int CH = 256 * kPPT;
+        const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
+        p.dep_scale = (T)(std::ldexp(1.0, 48) / qm);
+        p.dep_inv = (T)(qm * std::ldexp(1.0, -48));
+        fill(work_, 8, 0u);
+        const int CH = 256 * ppt_;
         const int64_t nch = (n_bound_ + CH - 1) / CH;
         const int grid = (int)std::max<int64_t>(8, std::min<int64_t>(8 * ((nch + 7) / 8), 8 * 256));
-        const size_t shm = p.lds_cap > 0 ? 9 * (size_t)lds_cap_ * sizeof(T) : 0;
-        k_push<T, kPPT><<<grid, 256, shm, stream>>>(p);
+        const size_t shm = p.lds_cap > 0 ? lds_push_bytes<T>(lds_cap_) : 0;
+        if (ppt_ == 4) k_push<T, 4><<<grid, 256, shm, stream>>>(p);
+        else if (ppt_ == 16) k_push<T, 16><<<grid, 256, shm, stream>>>(p);
+        else k_push<T, 8><<<grid, 256, shm, stream>>>(p);
         HIPCHK(hipGetLastError());
     }
 
@@ -833,7 +859,8 @@ pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc
             !(g.c > 0) || g.n_filt < 0 || g.n_filt > 8 || g.absorb_cells < 0 || g.absorb_cells > g.nr ||
             g.particle_capacity < 0 || (g.precision != PIC_FP64 && g.precision != PIC_FP32) ||
             (g.mover != PIC_VAY && g.mover != PIC_BORIS) || (g.r_kind != PIC_R_LOG && g.r_kind != PIC_R_LIN) ||
-            (g.th_kind != PIC_TH_EQAREA && g.th_kind != PIC_TH_LIN) || g.tile_r < 0 || g.tile_th < 0)
+            (g.th_kind != PIC_TH_EQAREA && g.th_kind != PIC_TH_LIN) || g.tile_r < 0 || g.tile_th < 0 ||
+            !(g.chunk_ppt == 0 || g.chunk_ppt == 4 || g.chunk_ppt == 8 || g.chunk_ppt == 16))
             throw StatusError{PIC_EINVAL, "invalid grid descriptor"};
         if (phys->bg_kind < PIC_BG_NONE || phys->bg_kind > PIC_BG_DIPOLE_COROT || !(phys->q_inj > 0 || !phys->inject))
             throw StatusError{PIC_EINVAL, "invalid physics descriptor"};
