@@ -39,57 +39,6 @@ struct Fields {
     T *c[9];
 };
 
-// Analytic initial ("vacuum") field of the rotating conductor, Sec. 5.2 and
-// Sec. 4.3; local (r, theta, phi) components at radius r, cos/sin theta.
-struct Background {
-    int kind;          // PIC_BG_*
-    double B0, r0;     // surface field and conductor radius
-};
-
-template <typename T>
-__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T k, T s, T E[3],
-                                      T B[3])
-{
-    const T B0 = (T)bg.B0, r0 = (T)bg.r0;
-    switch (bg.kind) {
-    case 1: // uniform B along the axis
-        B[0] += B0 * k;
-        B[1] -= B0 * s;
-        break;
-    case 2: { // monopole: inside corotation, outside the vacuum l = 1 field
-        const T q = r0 / r;
-        B[0] += B0 * q * q;
-        if (inside) {
-            E[1] -= B0 * r0 * q * s * inv_rl;
-        } else {
-            const T a = B0 * r0 * q * q * q * inv_rl;
-            E[0] -= (T)2 * a * k;
-            E[1] -= a * s;
-        }
-        break;
-    }
-    case 3:
-    case 4: { // dipole; corotation inside (or everywhere for the drift test), l = 2 vacuum outside
-        const T q = r0 / r;
-        const T q3 = q * q * q;
-        B[0] += (T)2 * B0 * q3 * k;
-        B[1] += B0 * q3 * s;
-        if (inside || bg.kind == 4) {
-            const T a = B0 * r0 * q * q * inv_rl;
-            E[0] += a * s * s;
-            E[1] -= (T)2 * a * s * k;
-        } else {
-            const T a = (T)2 * B0 * r0 * q3 * q * inv_rl;
-            E[0] -= a * (T)0.5 * ((T)3 * k * k - (T)1);
-            E[1] -= a * s * k;
-        }
-        break;
-    }
-    default:
-        break;
-    }
-}
-
 // ---------------------------------------------------------------------
 // Math policy.  FP32: hardware reciprocal, reciprocal square root and
 // square root (1 ulp), exp via v_exp_f32, and short series for the small
@@ -149,6 +98,57 @@ struct FM<double> {
     static __device__ __forceinline__ double log1p(double e) { return ::log1p(e); }
     static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
 };
+
+// Analytic initial ("vacuum") field of the rotating conductor, Sec. 5.2 and
+// Sec. 4.3; local (r, theta, phi) components at radius r, cos/sin theta.
+struct Background {
+    int kind;          // PIC_BG_*
+    double B0, r0;     // surface field and conductor radius
+};
+
+template <typename T>
+__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T k, T s, T E[3],
+                                      T B[3])
+{
+    const T B0 = (T)bg.B0, r0 = (T)bg.r0;
+    switch (bg.kind) {
+    case 1: // uniform B along the axis
+        B[0] += B0 * k;
+        B[1] -= B0 * s;
+        break;
+    case 2: { // monopole: inside corotation, outside the vacuum l = 1 field
+        const T q = r0 * FM<T>::rcp(r);
+        B[0] += B0 * q * q;
+        if (inside) {
+            E[1] -= B0 * r0 * q * s * inv_rl;
+        } else {
+            const T a = B0 * r0 * q * q * q * inv_rl;
+            E[0] -= (T)2 * a * k;
+            E[1] -= a * s;
+        }
+        break;
+    }
+    case 3:
+    case 4: { // dipole; corotation inside (or everywhere for the drift test), l = 2 vacuum outside
+        const T q = r0 * FM<T>::rcp(r);
+        const T q3 = q * q * q;
+        B[0] += (T)2 * B0 * q3 * k;
+        B[1] += B0 * q3 * s;
+        if (inside || bg.kind == 4) {
+            const T a = B0 * r0 * q * q * inv_rl;
+            E[0] += a * s * s;
+            E[1] -= (T)2 * a * s * k;
+        } else {
+            const T a = (T)2 * B0 * r0 * q3 * q * inv_rl;
+            E[0] -= a * (T)0.5 * ((T)3 * k * k - (T)1);
+            E[1] -= a * s * k;
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
 
 // ---------------------------------------------------------------------
 // Movers (Cartesian).  u = gamma v / c, eps = q dt / (2 m c).

@@ -228,16 +228,32 @@ struct LdsView {
 };
 
 // Deposit planes in LDS hold 64-bit fixed point: a contribution v is stored
-// as round(v * scale) with scale = 2^48 / max|w|, so integer LDS atomics
-// (much faster than floating-point ones) accumulate it exactly; a chunk of
-// at most 4096 particles, each adding at most four contributions of at most
-// max|w| to an entry, stays below 2^62.
+// as round(v * scale), so integer LDS atomics (much faster than floating-
+// point ones) accumulate it exactly.  Every contribution is at most max|w|
+// in magnitude.  FP32: scale = 2^30 / max|w|, so one contribution fits an
+// int32 (one hardware conversion) and resolves 1e-9 max|w|, below FP32
+// rounding.  FP64: scale = 2^48 / max|w|, converted exactly with the
+// 1.5 * 2^52 shift (valid below 2^51).  A chunk of at most 4096 particles,
+// each adding at most four contributions to an entry, stays below 2^62.
 template <typename T>
 __device__ __forceinline__ long long to_fixed(T v, T scale);
 template <>
-__device__ __forceinline__ long long to_fixed<float>(float v, float scale) { return __float2ll_rn(v * scale); }
+__device__ __forceinline__ long long to_fixed<float>(float v, float scale)
+{
+    return (long long)(int)__builtin_rintf(v * scale);
+}
 template <>
-__device__ __forceinline__ long long to_fixed<double>(double v, double scale) { return __double2ll_rn(v * scale); }
+__device__ __forceinline__ long long to_fixed<double>(double v, double scale)
+{
+    const double shifted = v * scale + 6755399441055744.0; // 1.5 * 2^52: the integer lands in the low bits
+    return (long long)(__double_as_longlong(shifted) - 0x4338000000000000ll);
+}
+template <typename T>
+constexpr int fixed_bits();
+template <>
+constexpr int fixed_bits<float>() { return 30; }
+template <>
+constexpr int fixed_bits<double>() { return 48; }
 
 template <typename T>
 struct LdsDep {
@@ -472,12 +488,10 @@ __host__ __device__ constexpr size_t lds_push_bytes(int cap)
 }
 
 // Slot of iteration q of thread t inside a chunk: each pass of the 256
-// threads reads every other particle of a 512-particle block (even ones,
-// then odd ones), so the two members of a co-located pair -- stored next to
-// each other -- never deposit in the same LDS atomic instruction.
+// threads reads 256 consecutive particles (full cache lines in and out).
 __device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
 {
-    return base + 512 * (size_t)(q >> 1) + 2 * tid + (q & 1);
+    return base + 256 * (size_t)q + tid;
 }
 
 // One work-group per chunk of 256 * PPT consecutive (cell-sorted) particles.
@@ -494,7 +508,6 @@ __device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
 template <typename T, int PPT>
 __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
 {
-    static_assert(PPT % 2 == 0, "chunks are read in even/odd passes");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);                              // 6 field planes
     long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>(p.lds_cap)); // 3 deposit planes

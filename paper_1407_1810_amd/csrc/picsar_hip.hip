@@ -760,8 +760,8 @@ private:
         p.work = work_;
         p.lds_cap = use_lds_ ? lds_cap_ : 0;
         const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
-        p.dep_scale = (T)(std::ldexp(1.0, 48) / qm);
-        p.dep_inv = (T)(qm * std::ldexp(1.0, -48));
+        p.dep_scale = (T)(std::ldexp(1.0, fixed_bits<T>()) / qm);
+        p.dep_inv = (T)(qm * std::ldexp(1.0, -fixed_bits<T>()));
         fill(work_, 8, 0u);
         const int CH = 256 * ppt_;
         const int64_t nch = (n_bound_ + CH - 1) / CH;
