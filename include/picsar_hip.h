@@ -41,7 +41,9 @@
  *    momenta and the weight to FP32 once, on the way in.
  *  - pic_step() enqueues on the context's stream and synchronises before it
  *    returns, so that device-side errors (CFL, capacity) are reported by
- *    the call that caused them.
+ *    the call that caused them.  Without stage timing the launches of one
+ *    step are captured once into a HIP graph and replayed; with timing on
+ *    they are enqueued one by one between HIP events.
  */
 #ifndef PICSAR_HIP_H
 #define PICSAR_HIP_H
@@ -170,8 +172,46 @@ pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
 /* Message of the last failed call on ctx (empty if none). */
 const char *pic_last_error(const pic_ctx *ctx);
 
-/* Release every resource of the context. */
+/* Release every resource of the context.  A context that belongs to a
+ * batch must outlive the batch. */
 void pic_destroy(pic_ctx *ctx);
+
+/* ------------------------------------------------------------------
+ * Batches: many independent runs advanced together (the ensemble of
+ * uneven runs of one precision on one device).  Every kernel of a step
+ * serves all runs of the batch at once -- field kernels over the
+ * concatenated work-groups of all grids, the push over the concatenated
+ * particle chunks of all runs -- so small runs fill the GPU together and a
+ * step costs one launch sequence, captured once into a HIP graph and
+ * replayed.  Each run keeps its own grid, physics, tile, sort interval and
+ * particle store (those of its context); the push uses the chunk_ppt of
+ * the first run.  Results are those of stepping each context on its own,
+ * up to the order of floating-point atomic additions.
+ * ------------------------------------------------------------------ */
+typedef struct pic_batch pic_batch;
+
+/* Group n initialised contexts (same device, same precision, no context
+ * twice) into *out.  The contexts stay valid for pic_get_* and may still be
+ * stepped alone; they must not be stepped concurrently with the batch and
+ * must outlive it.  hip_stream as in pic_create.  PIC_EINVAL for an empty
+ * or mixed list, PIC_ESTATE for a context without pic_init. */
+pic_status pic_batch_create(pic_ctx *const *runs, int32_t n, void *hip_stream, pic_batch **out);
+
+/* Advance every run of the batch by n_steps steps and synchronise.  A
+ * device error (CFL, injection capacity) of any run is reported with the
+ * index of the first run that raised it; all runs have then taken the
+ * steps. */
+pic_status pic_batch_step(pic_batch *b, int32_t n_steps);
+
+/* Device time in ms of the last pic_batch_step, from HIP events on the
+ * batch stream around its launches. */
+pic_status pic_batch_elapsed_ms(pic_batch *b, double *ms);
+
+/* Message of the last failed call on b (empty if none). */
+const char *pic_batch_last_error(const pic_batch *b);
+
+/* Release the batch (not its contexts). */
+void pic_batch_destroy(pic_batch *b);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,8 @@ STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "
 
 EXPORTED = ["pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
             "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
-            "pic_set_timing", "pic_last_error", "pic_destroy"]
+            "pic_set_timing", "pic_last_error", "pic_destroy", "pic_batch_create", "pic_batch_step",
+            "pic_batch_elapsed_ms", "pic_batch_last_error", "pic_batch_destroy"]
 
 
 class PicError(RuntimeError):
@@ -78,9 +79,16 @@ def lib():
         L.pic_last_error.argtypes = [vp]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [vp]
+        L.pic_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
+        L.pic_batch_step.argtypes = [vp, i32]
+        L.pic_batch_elapsed_ms.argtypes = [vp, P(d)]
+        L.pic_batch_last_error.argtypes = [vp]
+        L.pic_batch_last_error.restype = C.c_char_p
+        L.pic_batch_destroy.argtypes = [vp]
         for name in ("pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape",
                      "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_moments",
-                     "pic_set_step_index", "pic_set_carry", "pic_set_timing"):
+                     "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_batch_create",
+                     "pic_batch_step", "pic_batch_elapsed_ms"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -222,6 +230,44 @@ class Sim:
         out = np.zeros(9)
         self._check(lib().pic_get_moments(self._h, MOM_STAGE_MS, _dp(out), 9))
         return dict(zip(STAGES, out.tolist()))
+
+
+class Batch:
+    """Several Sim objects (same precision, same device) stepped together by
+    one launch sequence per step (pic_batch_*).  The Sims stay usable for
+    reading fields, particles and counts; keep them alive while the batch
+    exists."""
+
+    def __init__(self, sims, stream=None):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        self._h = C.c_void_p()
+        rc = lib().pic_batch_create(arr, len(self.sims), stream, C.byref(self._h))
+        if rc != 0:
+            raise PicError(rc, "pic_batch_create failed")
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PicError(rc, lib().pic_batch_last_error(self._h).decode())
+
+    def step(self, n=1):
+        self._check(lib().pic_batch_step(self._h, int(n)))
+
+    def elapsed_ms(self):
+        out = C.c_double()
+        self._check(lib().pic_batch_elapsed_ms(self._h, C.byref(out)))
+        return out.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pic_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gpu_available() -> bool:

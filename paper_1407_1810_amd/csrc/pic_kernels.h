@@ -1,15 +1,26 @@
 // pic_kernels.h -- HIP kernels of the gfx950 PIC step.
 //
+// Every kernel serves a table of independent runs; a single simulation is
+// a table of one.  Field kernels find their run from a per-run prefix of
+// their work-groups, particle kernels from a per-run prefix of their chunks
+// or spans that the device computes each step, and the step index, the
+// sort decision and the particle-buffer flip live in device counters.  A
+// step is therefore a fixed sequence of launches, the same for one run or
+// many uneven ones, which a HIP graph holds and replays.
+//
+//  k_step_begin ... particle-step count, sort decision, sort-span prefix
+//  k_sort_* ....... counting sort of particles by tile (serpentine order)
+//  k_zero_F ....... clear the deposit planes
 //  k_faraday ...... half Faraday update of B (App. A, eq. (discreteeq))
-//  k_ampere ....... Ampere update of E with the filtered face charges, polar
-//                   caps (eq. (erpolarupdate)), walls, lossy layer on E
-//  k_absorb_b ..... lossy layer on B (eq. (EBcond)), layer rows only
-//  k_filter ....... one 1-2-1 pass with the polar remap (App. B)
 //  k_push ......... gather + Vay/Boris push + move + VB deposit, one
 //                   work-group per chunk of cell-sorted particles, fields and
 //                   face charges staged in LDS for the chunk's bounding box
-//  k_inject ....... surface pair injection (Sec. 5.3, eq. (volinjeq))
-//  k_sort_* ....... counting sort of particles by tile (serpentine order)
+//  k_filter ....... one 1-2-1 pass with the polar remap (App. B)
+//  k_ampere ....... Ampere update of E with the filtered face charges, polar
+//                   caps (eq. (erpolarupdate)), walls, lossy layer on E
+//  k_absorb_b ..... lossy layer on B (eq. (EBcond))
+//  k_inject ....... surface pair injection (Sec. 5.3, eq. (volinjeq)), then
+//                   the step index advances
 //  k_node_charge,
 //  k_gauss_flux ... FP64 Gauss diagnostic
 #pragma once
@@ -45,9 +56,109 @@ struct Metric {
     const T *ab_half; // lossy-layer factor at rho = i + 1/2
 };
 
-// ------------------------------------------------------------------
-// Field kernels
-// ------------------------------------------------------------------
+// Device counters of a run (unsigned long long each).
+enum : int {
+    kTotal = 0,         // slots in use: live particles plus those deleted since the last sort
+    kDeadSinceSort = 1,
+    kDeleted = 2,       // deletions before the last sort
+    kInjected = 3,
+    kLive = 4,          // live count produced by the sort's scan
+    kPartSteps = 5,     // particle-steps advanced
+    kStep = 6,          // step index n (time t = n dt)
+    kCur = 7,           // current particle buffer (0 or 1)
+    kNeedSort = 8,      // particles were appended since the last sort
+    kSortNow = 9,       // the current step sorts
+    kNumCounters = 16
+};
+
+// Counting-sort key of a packed cell: tiles of tile_r x tile_th cells over
+// rows -G..nr+G, numbered in serpentine order so that consecutive tiles
+// share an edge; deleted particles get the last key.
+struct TileMap {
+    int G, tile_r, tile_th, ntj, n_keys;
+    __device__ int key(uint32_t c) const
+    {
+        if (c == kDead) return n_keys;
+        const int ti = (cell_i(c) + G) / tile_r;
+        int tj = cell_j(c) / tile_th;
+        if (ti & 1) tj = ntj - 1 - tj;
+        return ti * ntj + tj;
+    }
+};
+
+// Everything the kernels need to know about one run.  The host fills it
+// once (and again when particles with a larger weight arrive); what changes
+// from step to step lives in the counters `ctr`.
+template <typename T>
+struct RunDev {
+    Layout L;
+    T *fld[9];            // E_r, E_th, E_ph, B_r, B_th, B_ph, F_r, F_th, F_ph
+    T *ftmp[3];           // second set of face-charge planes (filter ping-pong)
+    const T *ffin[3];     // where the filtered face charges end up after n_filt passes
+    Metric<T> m;
+    Background bg;
+    int r_kind, th_kind, mover, n_filt, absorb_cells;
+    T c, dxi, inv_dxi, nth_f, two_over_nth, pi_over_nth, inv_pi_over_nth, eps0;
+    double omega, t_spin, cd; // final angular velocity, spin-up time, light speed
+    uint32_t *cell[2];    // two particle stores; the sort scatters from one into the other
+    T *arr[2][6];         // offsets dx, dy, momenta u_r, u_th, u_ph, weight w
+    uint64_t *id[2];      // null when ids are not kept
+    long long capacity;
+    unsigned long long *ctr;
+    int *status;          // bit 0 CFL, bit 1 capacity (injection), bit 2 sort destination
+    int lds_cap;          // entries per LDS plane of the push, 0 = global-memory path
+    T dep_scale, dep_inv; // fixed-point scale of the LDS deposit planes and its inverse
+    TileMap tm;
+    int sort_interval;    // <= 0: never
+    unsigned int *counts, *cursor;
+    unsigned long long *offsets;
+    int inject;
+    const double *kn, *sn, *Aj; // cos / sin theta_j, dual face area of node j on the inner conductor
+    double rb0, f_inj, q_inj;
+    double *carry;
+    uint64_t seed;
+};
+
+// 1 / R_l = Omega(t) / c, Omega rising linearly over t_spin (Sec. 5.2).
+__host__ __device__ inline double inv_light_cylinder(double omega, double t_spin, double c, double t)
+{
+    const double om = (t_spin > 0.0 && t < t_spin) ? omega * t / t_spin : omega;
+    return om / c;
+}
+
+// Work-groups of a launch over many runs: run r owns [off[r], off[r+1]).
+__device__ inline int run_of(const int *__restrict__ off, int n_runs, int b)
+{
+    int lo = 0, hi = n_runs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ inline int run_of(const unsigned long long *__restrict__ off, int n_runs, unsigned long long b)
+{
+    int lo = 0, hi = n_runs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// (row, column) of thread (threadIdx.x, threadIdx.y) of a 64 x 4 block in
+// the local block lb of a run whose rows are `ncol` wide.
+struct Cell2 {
+    int i, j;
+};
+__device__ inline Cell2 block_cell(int lb, int ncol)
+{
+    const int nbx = (ncol + 63) / 64;
+    const int by = lb / nbx, bx = lb - by * nbx;
+    return Cell2{by * 4 + (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
+}
 
 template <typename T>
 __global__ void k_fill(T *__restrict__ p, size_t n, T v)
@@ -56,88 +167,174 @@ __global__ void k_fill(T *__restrict__ p, size_t n, T v)
         p[q] = v;
 }
 
+// ------------------------------------------------------------------
+// Step bookkeeping
+// ------------------------------------------------------------------
+
+// One thread: count the particle-steps this step advances, decide per run
+// whether it sorts, and lay the sort spans of the sorting runs end to end.
+template <typename T>
+__global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int span,
+                             unsigned long long *__restrict__ span_off)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long acc = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        unsigned long long *c = runs[r].ctr;
+        c[kPartSteps] += c[kTotal] - c[kDeadSinceSort];
+        const int K = runs[r].sort_interval;
+        const bool now = K > 0 && (c[kNeedSort] != 0 || c[kStep] % (unsigned long long)K == 0);
+        c[kSortNow] = now ? 1ull : 0ull;
+        span_off[r] = acc;
+        if (now) acc += (c[kTotal] + span - 1) / span;
+    }
+    span_off[n_runs] = acc;
+}
+
+// One thread: close the sort of every sorting run (the live count becomes
+// the particle count, deletions since the last sort join the total, the
+// buffers swap), then lay the push chunks of all runs end to end and reset
+// the per-XCD chunk counters.
+template <typename T>
+__global__ void k_sort_finish(const RunDev<T> *__restrict__ runs, int n_runs, int chunk,
+                              unsigned long long *__restrict__ chunk_off, unsigned int *__restrict__ work)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long acc = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        unsigned long long *c = runs[r].ctr;
+        if (c[kSortNow]) {
+            c[kDeleted] += c[kDeadSinceSort];
+            c[kDeadSinceSort] = 0;
+            c[kTotal] = c[kLive];
+            c[kCur] ^= 1ull;
+            c[kNeedSort] = 0;
+        }
+        chunk_off[r] = acc;
+        acc += (c[kTotal] + chunk - 1) / chunk;
+    }
+    chunk_off[n_runs] = acc;
+    for (int x = 0; x < 8; ++x) work[x] = 0;
+}
+
+// ------------------------------------------------------------------
+// Field kernels: 64 x 4 work-groups, run r owning work-groups
+// [off[r], off[r+1]) of the launch
+// ------------------------------------------------------------------
+
+// Clear the three deposit planes (256 threads x 4 entries per work-group).
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                const int *__restrict__ off)
+{
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    const size_t n = R.L.size();
+    const size_t b = (size_t)(blockIdx.x - off[r]) * 1024 + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const size_t e = b + 256 * q;
+        if (e < n) {
+            R.fld[cFR][e] = (T)0;
+            R.fld[cFTH][e] = (T)0;
+            R.fld[cFPH][e] = (T)0;
+        }
+    }
+}
+
 // B += hc * circulation(E) / area for B_r (i, j+1/2), B_th (i+1/2, j),
 // B_ph (i+1/2, j+1/2).  B_r is held at zero on the conductors and B_th on
 // the axis.
 template <typename T>
-__global__ __launch_bounds__(256) void k_faraday(Fields<T> f, Layout L, Metric<T> m, T hc)
+__global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                 const int *__restrict__ off, T hc_frac)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    const Layout L = R.L;
     const int nr = L.nr, nth = L.nth;
+    const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
+    const int i = q.i, j = q.j;
     if (i > nr || j > nth) return;
-    const T *Er = f.c[cER], *Eth = f.c[cETH], *Eph = f.c[cEPH];
+    const Metric<T> &m = R.m;
+    const T hc = hc_frac * R.c;
+    const T *Er = R.fld[cER], *Eth = R.fld[cETH], *Eph = R.fld[cEPH];
     if (i >= 1 && i < nr && j < nth) {
         const T circ = Eph[L.at(i, j)] * m.s[j] - Eph[L.at(i, j + 1)] * m.s[j + 1];
-        f.c[cBR][L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
+        R.fld[cBR][L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
     }
     if (i < nr && j >= 1 && j < nth) {
         const T circ = Eph[L.at(i + 1, j)] * m.r_node[i + 1 + L.G] - Eph[L.at(i, j)] * m.r_node[i + L.G];
-        f.c[cBTH][L.at(i, j)] += hc * circ * m.idr2[i];
+        R.fld[cBTH][L.at(i, j)] += hc * circ * m.idr2[i];
     }
     if (i < nr && j < nth) {
         const T a = Eth[L.at(i, j)] * m.r_node[i + L.G] - Eth[L.at(i + 1, j)] * m.r_node[i + 1 + L.G];
         const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * m.dr[i] * m.idth[j];
-        f.c[cBPH][L.at(i, j)] += hc * (a - b) * m.idr2[i];
+        R.fld[cBPH][L.at(i, j)] += hc * (a - b) * m.idr2[i];
     }
 }
 
 // E += (c circulation(B) - F) / area, then the lossy-layer factor on E.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ampere(Fields<T> f, const T *__restrict__ Fr, const T *__restrict__ Fth,
-                                                const T *__restrict__ Fph, Layout L, Metric<T> m, T c)
+__global__ __launch_bounds__(256) void k_ampere(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                const int *__restrict__ off)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    const Layout L = R.L;
     const int nr = L.nr, nth = L.nth;
+    const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
+    const int i = q.i, j = q.j;
     if (i > nr || j > nth) return;
-    const T *Br = f.c[cBR], *Bth = f.c[cBTH], *Bph = f.c[cBPH];
+    const Metric<T> &m = R.m;
+    const T c = R.c;
+    const T *Br = R.fld[cBR], *Bth = R.fld[cBTH], *Bph = R.fld[cBPH];
+    const T *Fr = R.ffin[0], *Fth = R.ffin[1], *Fph = R.ffin[2];
     if (i < nr) {
         const T t1 = j < nth ? m.sb[j] * Bph[L.at(i, j)] : (T)0;
         const T t0 = j > 0 ? m.sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
-        T &e = f.c[cER][L.at(i, j)];
+        T &e = R.fld[cER][L.at(i, j)];
         e = (e + (c * (t1 - t0) * m.invrb[i] - Fr[L.at(i, j)] * m.invA[i]) * m.idkb[j]) * m.ab_half[i];
     }
     if (i >= 1 && i < nr && j < nth) {
         const T circ = m.rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - m.rb[i + L.G] * Bph[L.at(i, j)];
-        T &e = f.c[cETH][L.at(i, j)];
+        T &e = R.fld[cETH][L.at(i, j)];
         e = (e + (c * circ - Fth[L.at(i, j)] * m.isb2pi[j]) * m.idrb2[i]) * m.ab_int[i];
     }
     if (i >= 1 && i < nr && j >= 1 && j < nth) {
         const T a = m.rb[i + L.G] * Bth[L.at(i, j)] - m.rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
         const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * m.drb[i] * m.idthb[j];
-        T &e = f.c[cEPH][L.at(i, j)];
+        T &e = R.fld[cEPH][L.at(i, j)];
         e = (e + (c * (a - b) - Fph[L.at(i, j)] * m.idthb[j]) * m.idrb2[i]) * m.ab_int[i];
     }
 }
 
-// Lossy layer on B, rows i0..nr only (the factor is 1 elsewhere).
+// Lossy layer on B over rows nr - absorb_cells - 1 .. nr (the factor is 1
+// below); runs without a layer own no work-groups.
 template <typename T>
-__global__ __launch_bounds__(256) void k_absorb_b(Fields<T> f, Layout L, Metric<T> m, int i0)
+__global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                  const int *__restrict__ off)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = i0 + blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > L.nr || j > L.nth) return;
-    if (j < L.nth) f.c[cBR][L.at(i, j)] *= m.ab_int[i];
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    const Layout L = R.L;
+    const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
+    const int i = L.nr - R.absorb_cells - 1 + q.i, j = q.j;
+    if (i < 0 || i > L.nr || j > L.nth) return;
+    const Metric<T> &m = R.m;
+    if (j < L.nth) R.fld[cBR][L.at(i, j)] *= m.ab_int[i];
     if (i < L.nr) {
-        f.c[cBTH][L.at(i, j)] *= m.ab_half[i];
-        if (j < L.nth) f.c[cBPH][L.at(i, j)] *= m.ab_half[i];
+        R.fld[cBTH][L.at(i, j)] *= m.ab_half[i];
+        if (j < L.nth) R.fld[cBPH][L.at(i, j)] *= m.ab_half[i];
     }
 }
 
-// One pass of the 1-2-1 filter on up to three arrays (blockIdx.z picks one).
-// kind 0: integer-j positions (F_r, F_ph, node charge), kind 1: half-integer
-// j (F_th).  In theta the array is extended by zeros, filtered, and what
-// spilled across a pole is folded back onto its mirror image, with a plus
-// sign for integer-j components and a minus sign for the theta component;
-// radially the array is extended by zeros beyond rows [-G, last_row].
-struct FilterSet {
-    const void *src[3];
-    void *dst[3];
-    int kind[3];
-    int last_row[3];
-};
-
+// One pass of the 1-2-1 filter.  kind 0: integer-j positions (F_r, F_ph,
+// node charge), kind 1: half-integer j (F_th).  In theta the array is
+// extended by zeros, filtered, and what spilled across a pole is folded
+// back onto its mirror image, with a plus sign for integer-j components and
+// a minus sign for the theta component; radially the array is extended by
+// zeros beyond rows [-G, last row].
 template <typename T>
 __device__ inline T theta_pass(const T *__restrict__ a, const Layout &L, int i, int j, int kind)
 {
@@ -157,27 +354,52 @@ __device__ inline T theta_pass(const T *__restrict__ a, const Layout &L, int i, 
     return v;
 }
 
+// One pass over the three face-charge planes of every run that filters at
+// least pass + 1 times (blockIdx.y = component).  Pass p reads the planes
+// written by pass p - 1: even passes go from the deposit planes to the
+// second set, odd passes back.
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(FilterSet fs, Layout L)
+__global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                const int *__restrict__ off, int pass)
 {
-    const int z = blockIdx.z;
-    const int kind = fs.kind[z];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = -L.G + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    if (pass >= R.n_filt) return;
+    const Layout L = R.L;
+    const int comp = blockIdx.y;
+    const int kind = comp == 1 ? 1 : 0;
+    const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
+    const int i = -L.G + q.i, j = q.j;
     const int ncol = kind ? L.nth : L.nth + 1;
-    const int last = fs.last_row[z];
+    const int last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
     if (i > last || j >= ncol) return;
-    const T *a = (const T *)fs.src[z];
+    const T *a = (pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp];
+    T *dst = (pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp];
     T v = (T)0.5 * theta_pass(a, L, i, j, kind);
     if (i > -L.G) v += (T)0.25 * theta_pass(a, L, i - 1, j, kind);
     if (i < last) v += (T)0.25 * theta_pass(a, L, i + 1, j, kind);
-    ((T *)fs.dst[z])[L.at(i, j)] = v;
+    dst[L.at(i, j)] = v;
+}
+
+// The same pass on one integer-j array (the Gauss diagnostic's node charge).
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter_nodes(const T *__restrict__ src, T *__restrict__ dst, Layout L)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = -L.G + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int last = L.nr + L.G;
+    if (i > last || j > L.nth) return;
+    T v = (T)0.5 * theta_pass(src, L, i, j, 0);
+    if (i > -L.G) v += (T)0.25 * theta_pass(src, L, i - 1, j, 0);
+    if (i < last) v += (T)0.25 * theta_pass(src, L, i + 1, j, 0);
+    dst[L.at(i, j)] = v;
 }
 
 // ------------------------------------------------------------------
 // Particle push
 // ------------------------------------------------------------------
 
+// A run as one particle sees it.
 template <typename T>
 struct PushArgs {
     Layout L;
@@ -190,13 +412,44 @@ struct PushArgs {
     uint32_t *cell;
     T *dx, *dy, *ur, *ut, *up;
     const T *w;
-    const unsigned long long *n_total;
     unsigned long long *n_dead;
     int *status;
-    unsigned int *work;   // 8 chunk counters (one per XCD), zero at launch
-    int lds_cap;          // entries per LDS plane, 0 = gather/deposit in global memory
-    T dep_scale, dep_inv; // fixed-point scale of the LDS deposit planes and its inverse
 };
+
+template <typename T>
+__device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step)
+{
+    PushArgs<T> p;
+    p.L = R.L;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) p.f.c[q] = R.fld[q];
+    p.bg = R.bg;
+    p.r_kind = R.r_kind;
+    p.th_kind = R.th_kind;
+    p.mover = R.mover;
+    p.n_filt = R.n_filt;
+    p.c = R.c;
+    p.dxi = R.dxi;
+    p.inv_dxi = R.inv_dxi;
+    p.nth_f = R.nth_f;
+    p.two_over_nth = R.two_over_nth;
+    p.pi_over_nth = R.pi_over_nth;
+    p.inv_pi_over_nth = R.inv_pi_over_nth;
+    p.eps0 = R.eps0;
+    p.inv_rl = (T)inv_light_cylinder(R.omega, R.t_spin, R.cd, step);
+    p.r_node = R.m.r_node;
+    p.k_node = R.m.k;
+    p.cell = R.cell[cur];
+    p.dx = R.arr[cur][0];
+    p.dy = R.arr[cur][1];
+    p.ur = R.arr[cur][2];
+    p.ut = R.arr[cur][3];
+    p.up = R.arr[cur][4];
+    p.w = R.arr[cur][5];
+    p.n_dead = R.ctr + kDeadSinceSort;
+    p.status = R.status;
+    return p;
+}
 
 template <typename T>
 struct GlobalView {
@@ -494,40 +747,49 @@ __device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
     return base + 256 * (size_t)q + tid;
 }
 
-// One work-group per chunk of 256 * PPT consecutive (cell-sorted) particles.
-// The chunk's cell bounding box, widened by one cell below and two above
-// (gather stencils and one-cell moves), is staged in LDS when it fits:
-// six field planes with the axis mirror applied, and three face-charge
-// planes that collect the chunk's deposits with LDS atomics and are flushed
-// with one global atomic per non-zero entry.  Chunks that do not fit (an
-// unsorted tail) gather and deposit in global memory.  The particle array is
-// cut into eight contiguous chunk ranges, one per XCD, so that neighbouring
-// chunks share an L2; work-group b takes chunks of range b % 8 from that
-// range's atomic counter until the range is exhausted, so late-starting
-// work-groups never leave a tail of unbalanced work.
+
+// One work-group per chunk of 256 * PPT consecutive (cell-sorted) particles
+// of one run.  The chunk's cell bounding box, widened by one cell below and
+// two above (gather stencils and one-cell moves), is staged in LDS when it
+// fits: six field planes with the axis mirror applied, and three deposit
+// planes that collect the chunk's face charges and are flushed with one
+// global atomic per non-zero entry.  Chunks that do not fit (an unsorted
+// tail) gather and deposit in global memory.  The chunks of all runs form
+// one list (prefix chunk_off), cut into eight contiguous ranges, one per
+// XCD, so that neighbouring chunks share an L2; work-group b takes chunks of
+// range b % 8 from that range's atomic counter until the range is
+// exhausted, so late-starting work-groups never leave a tail of unbalanced
+// work.
 template <typename T, int PPT>
-__global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
+__global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs, int n_runs,
+                                              const unsigned long long *__restrict__ chunk_off,
+                                              unsigned int *__restrict__ work)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);                              // 6 field planes
-    long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>(p.lds_cap)); // 3 deposit planes
     __shared__ int red[4][4];
     __shared__ unsigned int s_next;
     constexpr int CH = 256 * PPT;
-    const unsigned long long n = *p.n_total;
-    const long long nch = (long long)((n + CH - 1) / CH);
+    const unsigned long long nch = chunk_off[n_runs];
     const int xcd = blockIdx.x & 7;
-    const long long lo = nch * xcd / 8, hi = nch * (xcd + 1) / 8;
+    const unsigned long long lo = nch * xcd / 8, hi = nch * (xcd + 1) / 8;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int cap = p.lds_cap;
-    const int nth = p.L.nth;
     for (;;) {
-        if (tid == 0) s_next = atomicAdd(&p.work[xcd], 1u);
+        if (tid == 0) s_next = atomicAdd(&work[xcd], 1u);
         __syncthreads();
-        const long long ch = lo + (long long)s_next;
+        const unsigned long long gch = lo + (unsigned long long)__builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
-        if (ch >= hi) break;
-        const size_t base = (size_t)ch * CH;
+        if (gch >= hi) break;
+        const int r = __builtin_amdgcn_readfirstlane(run_of(chunk_off, n_runs, gch));
+        const RunDev<T> &R = runs[r];
+        const unsigned long long *ctr = R.ctr;
+        const unsigned long long n = ctr[kTotal];
+        const int cur = (int)ctr[kCur];
+        const PushArgs<T> p = push_args(R, cur, (double)ctr[kStep]);
+        const int cap = R.lds_cap;
+        const int nth = p.L.nth;
+        T *sm = reinterpret_cast<T *>(smem_raw);                                 // 6 field planes
+        long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>(cap)); // 3 deposit planes
+        const size_t base = (size_t)(gch - chunk_off[r]) * CH;
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
 #pragma unroll
@@ -554,9 +816,9 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
             jmax = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
             __syncthreads();
             if (imin <= imax) {
-                const int R = imax - imin + 4;
+                const int Rr = imax - imin + 4;
                 C = jmax - jmin + 4;
-                use = (long long)R * C <= cap;
+                use = (long long)Rr * C <= cap;
                 i0 = imin - 1;
                 j0 = jmin - 1;
             }
@@ -589,7 +851,7 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
             }
             __syncthreads();
             const LdsView<T> view{sm, cap, i0, j0, C};
-            const LdsDep<T> dep{sd, cap, i0, j0, C, p.dep_scale};
+            const LdsDep<T> dep{sd, cap, i0, j0, C, R.dep_scale};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const size_t idx = chunk_slot(base, tid, q);
@@ -598,13 +860,14 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
             }
             __syncthreads();
             {
+                const T inv = R.dep_inv;
                 int fr = tid / C, fc = tid - (tid / C) * C;
                 for (int e = tid; e < RC; e += 256) {
                     const size_t g = p.L.at(i0 + fr, j0 + fc);
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) {
                         const long long v = sd[comp * cap + e];
-                        if (v != 0) unsafeAtomicAdd(&p.f.c[cFR + comp][g], (T)v * p.dep_inv);
+                        if (v != 0) unsafeAtomicAdd(&p.f.c[cFR + comp][g], (T)v * inv);
                     }
                     fr += dr;
                     fc += dc;
@@ -626,49 +889,40 @@ __global__ __launch_bounds__(256) void k_push(PushArgs<T> p)
 }
 
 // ------------------------------------------------------------------
-// Surface injection (one work-group of 1024 threads)
+// Surface injection: one work-group of 1024 threads per run; afterwards
+// the step index of every run advances
 // ------------------------------------------------------------------
-
-template <typename T>
-struct InjectArgs {
-    Layout L;
-    const T *Er;
-    Background bg;
-    double inv_rl;        // Omega(t_{n+1}) / c
-    double rb0;           // r(1/2): position of E_r next to the conductor
-    const double *kn, *sn; // cos / sin theta_j
-    const double *Aj;     // dual face area of node j on the inner conductor
-    double f_inj, q_inj;
-    double *carry;
-    uint64_t seed, step;
-    uint32_t *cell;
-    T *dx, *dy, *ur, *ut, *up, *w;
-    uint64_t *id;         // may be null
-    unsigned long long *n_total, *n_injected;
-    long long capacity;
-    int *status;
-};
 
 constexpr int kInjMaxPer = 8; // nth + 1 <= 8192
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_inject(InjectArgs<T> a)
+__global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ runs)
 {
     __shared__ long long scan[1024];
     __shared__ int ok;
+    const RunDev<T> &R = runs[blockIdx.x];
+    unsigned long long *ctr = R.ctr;
     const int tid = threadIdx.x;
-    const int nth = a.L.nth, nodes = nth + 1;
+    const uint64_t step = ctr[kStep];
+    if (!R.inject) {
+        if (tid == 0) ctr[kStep] = step + 1;
+        return;
+    }
+    const Layout L = R.L;
+    const int cur = (int)ctr[kCur];
+    const double irl = inv_light_cylinder(R.omega, R.t_spin, R.cd, (double)(step + 1));
+    const int nth = L.nth, nodes = nth + 1;
     const int per = (nodes + 1023) / 1024;
     const int j0 = tid * per, j1 = min(j0 + per, nodes);
     long long m[kInjMaxPer];
     long long mine = 0;
     for (int jj = j0; jj < j1; ++jj) {
         double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-        add_background(a.bg, a.inv_rl, false, a.rb0, a.kn[jj], a.sn[jj], E, B);
-        const double sigma = (double)a.Er[a.L.at(0, jj)] + E[0];
-        const double cnew = a.carry[jj] + a.f_inj * fabs(sigma) * a.Aj[jj] / a.q_inj;
+        add_background(R.bg, irl, false, R.rb0, R.kn[jj], R.sn[jj], E, B);
+        const double sigma = (double)R.fld[cER][L.at(0, jj)] + E[0];
+        const double cnew = R.carry[jj] + R.f_inj * fabs(sigma) * R.Aj[jj] / R.q_inj;
         const double fl = floor(cnew);
-        a.carry[jj] = cnew - fl;
+        R.carry[jj] = cnew - fl;
         m[jj - j0] = (long long)fl;
         mine += (long long)fl;
     }
@@ -682,19 +936,25 @@ __global__ __launch_bounds__(1024) void k_inject(InjectArgs<T> a)
     }
     const long long total = scan[1023];
     long long off = scan[tid] - mine;
-    const unsigned long long nbase = *a.n_total;
-    if (tid == 0) ok = (long long)nbase + 2 * total <= a.capacity;
+    const unsigned long long nbase = ctr[kTotal];
+    if (tid == 0) ok = (long long)nbase + 2 * total <= R.capacity;
     __syncthreads();
     if (!ok) {
-        if (tid == 0) atomicOr(a.status, 2);
+        if (tid == 0) {
+            atomicOr(R.status, 2);
+            ctr[kStep] = step + 1;
+        }
         return;
     }
+    uint32_t *cell = R.cell[cur];
+    T *const *a = R.arr[cur];
+    uint64_t *id = R.id[cur];
     for (int jj = j0; jj < j1; ++jj) {
         const double ylo = jj - 0.5 < 0.0 ? 0.0 : jj - 0.5;
         const double yhi = jj + 0.5 > nth ? (double)nth : jj + 0.5;
         for (long long kk = 0; kk < m[jj - j0]; ++kk) {
-            uint64_t x[4] = {a.step, (uint64_t)jj, (uint64_t)kk, 0};
-            philox4x64(x, a.seed, 0x50494353ull);
+            uint64_t x[4] = {step, (uint64_t)jj, (uint64_t)kk, 0};
+            philox4x64(x, R.seed, 0x50494353ull);
             const double U = (double)(x[0] >> 11) * 0x1.0p-53;
             const double y = ylo + U * (yhi - ylo);
             int jc = (int)floor(y);
@@ -702,40 +962,29 @@ __global__ __launch_bounds__(1024) void k_inject(InjectArgs<T> a)
             const T fy = (T)(y - jc);
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const size_t d = nbase + 2 * (size_t)(off + kk) + sgn;
-                a.cell[d] = pack_cell(0, jc);
-                a.dx[d] = (T)0.5;
-                a.dy[d] = fy;
-                a.ur[d] = a.ut[d] = a.up[d] = (T)0;
-                a.w[d] = sgn == 0 ? (T)a.q_inj : (T)-a.q_inj;
-                if (a.id)
-                    a.id[d] = 0x8000000000000000ull | (a.step << 36) | ((uint64_t)jj << 20) | ((uint64_t)kk << 1) |
-                              (uint64_t)sgn;
+                cell[d] = pack_cell(0, jc);
+                a[0][d] = (T)0.5;
+                a[1][d] = fy;
+                a[2][d] = a[3][d] = a[4][d] = (T)0;
+                a[5][d] = sgn == 0 ? (T)R.q_inj : (T)-R.q_inj;
+                if (id)
+                    id[d] = 0x8000000000000000ull | (step << 36) | ((uint64_t)jj << 20) | ((uint64_t)kk << 1) |
+                            (uint64_t)sgn;
             }
         }
         off += m[jj - j0];
     }
     __syncthreads();
     if (tid == 0) {
-        *a.n_total = nbase + 2 * total;
-        *a.n_injected += 2 * total;
+        ctr[kTotal] = nbase + 2 * total;
+        ctr[kInjected] += 2 * total;
+        ctr[kStep] = step + 1;
     }
 }
 
 // ------------------------------------------------------------------
-// Counting sort by tile
+// Counting sort by tile, for the runs whose kSortNow is set
 // ------------------------------------------------------------------
-
-struct TileMap {
-    int G, tile_r, tile_th, ntj, n_keys;
-    __device__ int key(uint32_t c) const
-    {
-        if (c == kDead) return n_keys;
-        const int ti = (cell_i(c) + G) / tile_r;
-        int tj = cell_j(c) / tile_th;
-        if (ti & 1) tj = ntj - 1 - tj; // serpentine: consecutive tiles share an edge
-        return ti * ntj + tj;
-    }
-};
 
 __device__ inline unsigned long long lanemask_le(int lane)
 {
@@ -743,25 +992,50 @@ __device__ inline unsigned long long lanemask_le(int lane)
 }
 
 // Particles per wave of the sort kernels: each wave walks a contiguous span
-// so that the particles of one tile (kept together by the previous sort) are
-// counted and placed by about one wave, not by dozens contending for the
-// same counter.
+// of one run so that the particles of one tile (kept together by the
+// previous sort) are counted and placed by about one wave, not by dozens
+// contending for the same counter.  The spans of all sorting runs are laid
+// end to end (prefix span_off).
 constexpr int kSortSpan = 64 * 64;
 
-// Histogram of tile keys.  Within a span the last run of each 64-particle
-// window is kept pending and extended by the next window while the key
-// stays the same; a counter is touched only when a run ends.
-__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *__restrict__ cell,
-                                                   const unsigned long long *n_total, TileMap tm,
-                                                   unsigned int *__restrict__ counts)
+// Clear the tile counters and cursors of the sorting runs (256 per
+// work-group).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                   const int *__restrict__ off)
 {
-    const unsigned long long n = *n_total;
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    if (!R.ctr[kSortNow]) return;
+    const int e = (blockIdx.x - off[r]) * 256 + threadIdx.x;
+    if (e <= R.tm.n_keys) {
+        R.counts[e] = 0;
+        R.cursor[e] = 0;
+    }
+}
+
+// Histogram of tile keys.  Within a span the last run of equal keys of each
+// 64-particle window is kept pending and extended by the next window while
+// the key stays the same; a counter is touched only when a run of keys
+// ends.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                   const unsigned long long *__restrict__ span_off)
+{
     const int lane = threadIdx.x & 63;
     const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
     const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
-    for (unsigned long long s0 = wave * kSortSpan; s0 < n; s0 += nwaves * kSortSpan) {
+    const unsigned long long nspan = span_off[n_runs];
+    for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
+        const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
+        const RunDev<T> &R = runs[r];
+        const unsigned long long n = R.ctr[kTotal];
+        const uint32_t *cell = R.cell[R.ctr[kCur]];
+        const TileMap tm = R.tm;
+        unsigned int *counts = R.counts;
+        const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
         const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
-        int pend_key = -1;          // wave-uniform pending run
+        int pend_key = -1;          // wave-uniform pending run of keys
         unsigned int pend_len = 0;
         for (unsigned long long b = s0; b < s1; b += 64) {
             const unsigned long long idx = b + lane;
@@ -793,12 +1067,16 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *__restrict__ 
 }
 
 // Exclusive scan of counts[0..n_keys] (the last key collects deleted
-// particles) into offsets; n_total becomes the number of live particles.
-__global__ __launch_bounds__(1024) void k_sort_scan(const unsigned int *__restrict__ counts, int n_keys,
-                                                    unsigned long long *__restrict__ offsets,
-                                                    unsigned long long *n_total, unsigned long long *n_live_out)
+// particles) into offsets, one work-group per run; kLive becomes the number
+// of live particles.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict__ runs)
 {
     __shared__ unsigned long long s[1024];
+    const RunDev<T> &R = runs[blockIdx.x];
+    if (!R.ctr[kSortNow]) return;
+    const int n_keys = R.tm.n_keys;
+    const unsigned int *counts = R.counts;
     const int tid = threadIdx.x;
     const int per = (n_keys + 1 + 1023) / 1024;
     const int a = tid * per, b = min(a + per, n_keys + 1);
@@ -814,76 +1092,57 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const unsigned int *__restri
     }
     unsigned long long run = s[tid] - mine;
     for (int q = a; q < b; ++q) {
-        offsets[q] = run;
+        R.offsets[q] = run;
         run += counts[q];
     }
     __syncthreads();
-    if (tid == 0) {
-        // offsets[n_keys] = first slot of the deleted ones = number of live particles
-        *n_live_out = s[1023] - counts[n_keys];
-    }
+    if (tid == 0) R.ctr[kLive] = s[1023] - counts[n_keys];
 }
 
-// Live particles at the start of a step, accumulated: the particle-steps
-// actually advanced.
-__global__ void k_count_live(unsigned long long *ctr) { ctr[5] += ctr[0] - ctr[1]; }
-
-// After the scatter: live count becomes the particle count; deletions since
-// the last sort move to the running total.  ctr = {total, dead since sort,
-// deleted, injected, live}.
-__global__ void k_finish_sort(unsigned long long *ctr)
-{
-    ctr[2] += ctr[1];
-    ctr[1] = 0;
-    ctr[0] = ctr[4];
-}
-
+// Stable scatter into the other buffer: each run of equal keys in a
+// 64-particle window claims its slots with one atomic.
 template <typename T>
-struct SortArgs {
-    const uint32_t *cell;
-    const T *a[6];
-    const uint64_t *id;
-    uint32_t *cell_o;
-    T *a_o[6];
-    uint64_t *id_o;
-    const unsigned long long *n_total;
-    const unsigned long long *offsets;
-    unsigned int *cursor;
-    TileMap tm;
-    unsigned long long capacity;
-    int *status;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_sort_scatter(SortArgs<T> s)
+__global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                      const unsigned long long *__restrict__ span_off)
 {
-    const unsigned long long n = *s.n_total;
     const int lane = threadIdx.x & 63;
     const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
     const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
-    for (unsigned long long s0 = wave * kSortSpan; s0 < n; s0 += nwaves * kSortSpan) {
+    const unsigned long long nspan = span_off[n_runs];
+    for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
+        const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
+        const RunDev<T> &R = runs[r];
+        const unsigned long long n = R.ctr[kTotal];
+        const int cur = (int)R.ctr[kCur], nxt = cur ^ 1;
+        const uint32_t *cell = R.cell[cur];
+        uint32_t *cell_o = R.cell[nxt];
+        const uint64_t *id = R.id[cur];
+        uint64_t *id_o = R.id[nxt];
+        const TileMap tm = R.tm;
+        const unsigned long long cap = (unsigned long long)R.capacity;
+        const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
         const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
         for (unsigned long long b = s0; b < s1; b += 64) {
             const unsigned long long idx = b + lane;
-            const uint32_t c = idx < s1 ? s.cell[idx] : kDead;
-            const int key = idx < s1 ? s.tm.key(c) : INT_MAX;
+            const uint32_t c = idx < s1 ? cell[idx] : kDead;
+            const int key = idx < s1 ? tm.key(c) : INT_MAX;
             const int prev = __shfl_up(key, 1);
             const bool head = lane == 0 || key != prev;
             const unsigned long long heads = __ballot(head);
             const unsigned long long after = heads & ~lanemask_le(lane);
             const int next = after ? __ffsll((long long)after) - 1 : 64;
-            const bool live = key != INT_MAX && key != s.tm.n_keys;
+            const bool live = key != INT_MAX && key != tm.n_keys;
             unsigned int got = 0;
-            if (head && live) got = atomicAdd(&s.cursor[key], (unsigned int)(next - lane));
+            if (head && live) got = atomicAdd(&R.cursor[key], (unsigned int)(next - lane));
             const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
             got = __shfl(got, hl);
-            const unsigned long long d = live ? s.offsets[key] + got + (lane - hl) : 0;
-            if (live && d >= s.capacity) atomicOr(s.status, 4); // never write outside the store
-            if (live && d < s.capacity) {
-                s.cell_o[d] = c;
+            const unsigned long long d = live ? R.offsets[key] + got + (lane - hl) : 0;
+            if (live && d >= cap) atomicOr(R.status, 4); // never write outside the store
+            if (live && d < cap) {
+                cell_o[d] = c;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) s.a_o[q][d] = s.a[q][idx];
-                if (s.id) s.id_o[d] = s.id[idx];
+                for (int q = 0; q < 6; ++q) R.arr[nxt][q][d] = R.arr[cur][q][idx];
+                if (id) id_o[d] = id[idx];
             }
         }
     }

@@ -4,10 +4,14 @@
 // for the life of the context: nine field planes in one padded layout, a
 // second set of face-charge planes for the filter's ping-pong, two
 // structure-of-arrays particle stores (the counting sort scatters from one
-// into the other), FP64 metric tables built on the host, and a few device
-// counters.  A step is a fixed sequence of kernel launches on the
-// context's stream; control returns to the host only at the end of
-// pic_step.
+// into the other), metric tables built in FP64 on the host, and a few
+// device counters (particle counts, step index, current buffer).
+//
+// A step is a fixed sequence of launches over a table of runs (Plan): a
+// context steps a table of one, a batch steps the runs of many contexts
+// with the same launches.  Without stage timing the sequence is captured
+// once into a HIP graph and replayed; control returns to the host only at
+// the end of pic_step / pic_batch_step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +43,277 @@ struct HipError {
 struct StatusError {
     pic_status st;
     std::string msg;
+};
+
+template <typename U>
+U *dev_alloc(size_t n)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(U) * std::max<size_t>(n, 1)) != hipSuccess)
+        throw StatusError{PIC_ENOMEM, "device allocation failed"};
+    return (U *)p;
+}
+
+template <typename U>
+void dev_fill(U *p, size_t n, U v, hipStream_t s)
+{
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    k_fill<U><<<std::max(blocks, 1), 256, 0, s>>>(p, n, v);
+    HIPCHK(hipGetLastError());
+}
+
+// Per-stage device time from HIP events recorded between the launches of
+// eagerly enqueued steps.
+enum { kStSort = 0, kStFaraday, kStPush, kStFilter, kStAmpere, kStAbsorb, kStInject, kStZero, kStTotal, kStages };
+
+class StageTimer {
+public:
+    ~StageTimer()
+    {
+        for (auto &e : pool_) (void)hipEventDestroy(e);
+    }
+    void begin(int n_steps)
+    {
+        const size_t need = (size_t)n_steps * kStages * 2;
+        while (pool_.size() < need) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            pool_.push_back(e);
+        }
+        std::fill(used_, used_ + kStages, false);
+        base_ = 0;
+    }
+    void next_step(int s) { base_ = (size_t)s * kStages * 2; }
+    void mark(hipStream_t s, int q, bool start)
+    {
+        HIPCHK(hipEventRecord(pool_[base_ + 2 * q + (start ? 0 : 1)], s));
+        used_[q] = true;
+    }
+    // mean per step over the n steps just enqueued (the stream must be idle)
+    void finish(int n_steps, double *out)
+    {
+        for (int q = 0; q < kStages; ++q) {
+            out[q] = 0.0;
+            if (!used_[q] || n_steps <= 0) continue;
+            for (int s = 0; s < n_steps; ++s) {
+                float ms = 0.f;
+                const size_t b = (size_t)s * kStages * 2 + 2 * q;
+                HIPCHK(hipEventElapsedTime(&ms, pool_[b], pool_[b + 1]));
+                out[q] += ms;
+            }
+            out[q] /= n_steps;
+        }
+    }
+
+private:
+    std::vector<hipEvent_t> pool_;
+    size_t base_ = 0;
+    bool used_[kStages] = {};
+};
+
+// ------------------------------------------------------------------
+// Launch plan of one step over a table of runs
+// ------------------------------------------------------------------
+enum { kMapGrid = 0, kMapFilter, kMapAbsorb, kMapZero, kMapKeys, kMaps };
+
+template <typename T>
+class Plan {
+public:
+    Plan() = default;
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
+    ~Plan()
+    {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+        for (void *p : allocs_) (void)hipFree(p);
+    }
+
+    // Work-group maps, grids and LDS size for these runs; the table itself
+    // is uploaded by upload().
+    void build(const std::vector<RunDev<T>> &rd, int ppt, hipStream_t s)
+    {
+        n_ = (int)rd.size();
+        ppt_ = ppt;
+        runs_ = alloc<RunDev<T>>(n_);
+        maps_ = alloc<int>((size_t)kMaps * (n_ + 1));
+        chunk_off_ = alloc<unsigned long long>(n_ + 1);
+        span_off_ = alloc<unsigned long long>(n_ + 1);
+        work_ = alloc<unsigned int>(8);
+        std::vector<int> h((size_t)kMaps * (n_ + 1), 0);
+        long long cap_sum = 0, chunk_bound = 0;
+        int max_cap = 0;
+        const long long CH = 256LL * ppt_;
+        for (int m = 0; m < kMaps; ++m) tot_[m] = 0;
+        max_filt_ = 0;
+        any_sort_ = false;
+        for (int r = 0; r < n_; ++r) {
+            const RunDev<T> &R = rd[r];
+            const int nbx = (R.L.nth + 1 + 63) / 64;
+            const int cnt[kMaps] = {
+                nbx * ((R.L.nr + 1 + 3) / 4),
+                nbx * ((R.L.rows() + 3) / 4),
+                R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + 3) / 4) : 0,
+                (int)((R.L.size() + 1023) / 1024),
+                R.sort_interval > 0 ? (R.tm.n_keys + 1 + 255) / 256 : 0,
+            };
+            for (int m = 0; m < kMaps; ++m) {
+                h[(size_t)m * (n_ + 1) + r] = tot_[m];
+                tot_[m] += cnt[m];
+            }
+            max_filt_ = std::max(max_filt_, R.n_filt);
+            any_sort_ = any_sort_ || R.sort_interval > 0;
+            max_cap = std::max(max_cap, R.lds_cap);
+            cap_sum += std::max<long long>(R.capacity, 1);
+            chunk_bound += (std::max<long long>(R.capacity, 1) + CH - 1) / CH;
+        }
+        for (int m = 0; m < kMaps; ++m) h[(size_t)m * (n_ + 1) + n_] = tot_[m];
+        HIPCHK(hipMemcpyAsync(maps_, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+        shm_ = max_cap > 0 ? lds_push_bytes<T>(max_cap) : 0;
+        if (shm_ > 0) {
+            const int b = (int)shm_;
+            HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+            HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+            HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+        }
+        // one wave per sort span (four per work-group); the kernels loop over
+        // the spans of the step, so the grid only bounds the parallelism
+        sort_blocks_ = (int)std::min<long long>(std::max<long long>((cap_sum + 4 * kSortSpan - 1) / (4 * kSortSpan), 1),
+                                                4096);
+        // the push work-groups fetch chunks until their XCD's range is done:
+        // eight per CU at most, a multiple of eight
+        push_grid_ = (int)std::max<long long>(8, std::min<long long>(8 * ((chunk_bound + 7) / 8), 8 * 256));
+        upload(rd, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    void upload(const std::vector<RunDev<T>> &rd, hipStream_t s)
+    {
+        HIPCHK(hipMemcpyAsync(runs_, rd.data(), sizeof(RunDev<T>) * rd.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // n steps on stream s: eagerly with stage events when a timer is
+    // given, else by replaying the captured graph of one step
+    void run(int n, hipStream_t s, StageTimer *timer)
+    {
+        if (n <= 0) return;
+        if (timer) {
+            timer->begin(n);
+            for (int q = 0; q < n; ++q) {
+                timer->next_step(q);
+                enqueue(s, timer);
+            }
+            return;
+        }
+        if (!exec_) capture();
+        for (int q = 0; q < n; ++q) HIPCHK(hipGraphLaunch(exec_, s));
+    }
+
+private:
+    std::vector<void *> allocs_;
+    int n_ = 0, ppt_ = 8, max_filt_ = 0;
+    bool any_sort_ = false;
+    RunDev<T> *runs_ = nullptr;
+    int *maps_ = nullptr;
+    int tot_[kMaps] = {};
+    unsigned long long *chunk_off_ = nullptr, *span_off_ = nullptr;
+    unsigned int *work_ = nullptr;
+    size_t shm_ = 0;
+    int sort_blocks_ = 1, push_grid_ = 8;
+    hipStream_t cap_stream_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+
+    template <typename U>
+    U *alloc(size_t n)
+    {
+        U *p = dev_alloc<U>(n);
+        allocs_.push_back(p);
+        return p;
+    }
+    const int *map(int m) const { return maps_ + (size_t)m * (n_ + 1); }
+
+    void capture()
+    {
+        if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue(cap_stream_, nullptr);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cap_stream_, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
+        HIPCHK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+    }
+
+    void mark(StageTimer *t, hipStream_t s, int q, bool start)
+    {
+        if (t) t->mark(s, q, start);
+    }
+
+    // The launches of one step (order of Sec. 3 and App. A: half Faraday,
+    // push and deposit, half Faraday, filter, Ampere, lossy layer, then
+    // injection), preceded by the counting sort when a run is due.
+    void enqueue(hipStream_t s, StageTimer *t)
+    {
+        const dim3 blk2(64, 4);
+        mark(t, s, kStTotal, true);
+        mark(t, s, kStSort, true);
+        k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_);
+        HIPCHK(hipGetLastError());
+        if (any_sort_) {
+            if (tot_[kMapKeys] > 0) k_sort_zero<T><<<tot_[kMapKeys], 256, 0, s>>>(runs_, n_, map(kMapKeys));
+            k_sort_hist<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
+            k_sort_scan<T><<<n_, 1024, 0, s>>>(runs_);
+            k_sort_scatter<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
+            HIPCHK(hipGetLastError());
+        }
+        k_sort_finish<T><<<1, 64, 0, s>>>(runs_, n_, 256 * ppt_, chunk_off_, work_);
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStSort, false);
+        mark(t, s, kStZero, true);
+        k_zero_F<T><<<tot_[kMapZero], 256, 0, s>>>(runs_, n_, map(kMapZero));
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStZero, false);
+        mark(t, s, kStFaraday, true);
+        k_faraday<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid), (T)0.5);
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStFaraday, false);
+        mark(t, s, kStPush, true);
+        if (ppt_ == 4) k_push<T, 4><<<push_grid_, 256, shm_, s>>>(runs_, n_, chunk_off_, work_);
+        else if (ppt_ == 16) k_push<T, 16><<<push_grid_, 256, shm_, s>>>(runs_, n_, chunk_off_, work_);
+        else k_push<T, 8><<<push_grid_, 256, shm_, s>>>(runs_, n_, chunk_off_, work_);
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStPush, false);
+        k_faraday<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid), (T)0.5);
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStFilter, true);
+        for (int pss = 0; pss < max_filt_; ++pss) {
+            k_filter<T><<<dim3(tot_[kMapFilter], 3), blk2, 0, s>>>(runs_, n_, map(kMapFilter), pss);
+            HIPCHK(hipGetLastError());
+        }
+        mark(t, s, kStFilter, false);
+        mark(t, s, kStAmpere, true);
+        k_ampere<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid));
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStAmpere, false);
+        mark(t, s, kStAbsorb, true);
+        if (tot_[kMapAbsorb] > 0) {
+            k_absorb_b<T><<<tot_[kMapAbsorb], blk2, 0, s>>>(runs_, n_, map(kMapAbsorb));
+            HIPCHK(hipGetLastError());
+        }
+        mark(t, s, kStAbsorb, false);
+        mark(t, s, kStInject, true);
+        k_inject<T><<<n_, 1024, 0, s>>>(runs_);
+        HIPCHK(hipGetLastError());
+        mark(t, s, kStInject, false);
+        mark(t, s, kStTotal, false);
+    }
 };
 
 // ------------------------------------------------------------------
@@ -81,15 +356,18 @@ public:
     virtual void gauss(double *out) = 0;
     virtual void get_carry(double *out) = 0;
     virtual void set_carry(const double *in) = 0;
+    virtual void set_step(int64_t step) = 0;
     virtual void stage_ms(double *out) = 0;
+    // device status bits of the run (cleared on read)
+    virtual int take_status() = 0;
 
     pic_grid_desc gd{};
     pic_phys_desc ph{};
     hipStream_t stream = nullptr;
-    int64_t step_index = 0;
     bool timing = false;
     Layout L{};
     Geometry geo{};
+    unsigned version = 0; // bumped whenever the run's table entry changes
 
     void field_shape(int comp, int32_t *rows, int32_t *cols, int32_t *row0) const
     {
@@ -103,13 +381,19 @@ public:
     }
 };
 
+void raise_status(int st, const std::string &where)
+{
+    if (st & 1) throw StatusError{PIC_ECFL, where + "a particle moved one cell or more in one step (CFL)"};
+    if (st & 2) throw StatusError{PIC_ECAPACITY, where + "particle capacity exceeded by surface injection"};
+    if (st & 4) throw StatusError{PIC_EDEVICE, where + "internal error: sort destination outside the particle store"};
+}
+
 template <typename T>
 class EngineT final : public Engine {
 public:
     ~EngineT() override
     {
         for (void *p : allocs_) (void)hipFree(p);
-        for (auto &e : evpool_) (void)hipEventDestroy(e);
     }
 
     void init() override
@@ -127,55 +411,101 @@ public:
         geo.r_in = gd.r_in;
         geo.r_out = gd.r_out;
         geo.dxi = gd.r_kind == PIC_R_LOG ? std::log(gd.r_out / gd.r_in) / nr : (gd.r_out - gd.r_in) / nr;
-        tile_r_ = gd.tile_r > 0 ? gd.tile_r : 8;
-        tile_th_ = gd.tile_th > 0 ? gd.tile_th : 8;
-        sort_interval_ = gd.sort_interval == 0 ? 4 : gd.sort_interval;
+        const int tile_r = gd.tile_r > 0 ? gd.tile_r : 8;
+        const int tile_th = gd.tile_th > 0 ? gd.tile_th : 8;
+        const int sort_interval = gd.sort_interval == 0 ? 4 : gd.sort_interval;
         cap_ = gd.particle_capacity;
         if (ph.inject) qmax_ = std::fabs(ph.q_inj);
         with_ids_ = (gd.flags & PIC_FLAG_IDS) != 0;
+        ppt_ = gd.chunk_ppt > 0 ? gd.chunk_ppt : 8;
 
+        RunDev<T> &R = rd_;
+        R = RunDev<T>{};
+        R.L = L;
         const size_t fsz = L.size();
         for (int c = 0; c < 9; ++c) {
             fld_[c] = dalloc<T>(fsz);
             fill(fld_[c], fsz, (T)0);
+            R.fld[c] = fld_[c];
         }
         for (int c = 0; c < 3; ++c) {
             ftmp_[c] = dalloc<T>(fsz);
             fill(ftmp_[c], fsz, (T)0);
+            R.ftmp[c] = ftmp_[c];
+            // even pass counts end in the deposit planes, odd ones in the second set
+            R.ffin[c] = (gd.n_filt & 1) ? ftmp_[c] : fld_[6 + c];
         }
         build_tables();
+        R.m = m_;
+        R.bg = Background{ph.bg_kind, ph.B0, gd.r_in};
+        R.r_kind = gd.r_kind;
+        R.th_kind = gd.th_kind;
+        R.mover = gd.mover;
+        R.n_filt = gd.n_filt;
+        R.absorb_cells = std::min(gd.absorb_cells, nr);
+        R.c = (T)gd.c;
+        R.dxi = (T)geo.dxi;
+        R.inv_dxi = (T)(1.0 / geo.dxi);
+        R.nth_f = (T)nth;
+        R.two_over_nth = (T)(2.0 / nth);
+        R.pi_over_nth = (T)(kPi / nth);
+        R.inv_pi_over_nth = (T)(nth / kPi);
+        R.eps0 = (T)(ph.q_over_m / (2.0 * gd.c));
+        R.omega = ph.omega;
+        R.t_spin = ph.t_spin;
+        R.cd = gd.c;
         for (int s = 0; s < 2; ++s) {
             cell_[s] = dalloc<uint32_t>(std::max<int64_t>(cap_, 1));
-            for (int a = 0; a < 6; ++a) arr_[s][a] = dalloc<T>(std::max<int64_t>(cap_, 1));
+            R.cell[s] = cell_[s];
+            for (int a = 0; a < 6; ++a) {
+                arr_[s][a] = dalloc<T>(std::max<int64_t>(cap_, 1));
+                R.arr[s][a] = arr_[s][a];
+            }
             id_[s] = with_ids_ ? dalloc<uint64_t>(std::max<int64_t>(cap_, 1)) : nullptr;
+            R.id[s] = id_[s];
         }
-        ctr_ = dalloc<unsigned long long>(8);
-        fill(ctr_, 8, 0ull);
+        R.capacity = cap_;
+        ctr_ = dalloc<unsigned long long>(kNumCounters);
+        fill(ctr_, kNumCounters, 0ull);
+        fill(ctr_ + kNeedSort, 1, 1ull); // the first step sorts
+        R.ctr = ctr_;
         status_ = dalloc<int>(1);
         fill(status_, 1, 0);
-        work_ = dalloc<unsigned int>(8);
-        carry_ = dalloc<double>(nth + 1);
-        fill(carry_, (size_t)nth + 1, 0.0);
+        R.status = status_;
         // sort tiles over rows -G..nr+G
-        ntr_ = (L.rows() + tile_r_ - 1) / tile_r_;
-        ntj_ = (nth + tile_th_ - 1) / tile_th_;
-        n_keys_ = ntr_ * ntj_;
-        counts_ = dalloc<unsigned int>(n_keys_ + 1);
-        cursor_ = dalloc<unsigned int>(n_keys_ + 1);
-        offsets_ = dalloc<unsigned long long>(n_keys_ + 1);
+        const int ntr = (L.rows() + tile_r - 1) / tile_r;
+        const int ntj = (nth + tile_th - 1) / tile_th;
+        R.tm = TileMap{L.G, tile_r, tile_th, ntj, ntr * ntj};
+        R.sort_interval = sort_interval;
+        counts_ = dalloc<unsigned int>(R.tm.n_keys + 1);
+        cursor_ = dalloc<unsigned int>(R.tm.n_keys + 1);
+        offsets_ = dalloc<unsigned long long>(R.tm.n_keys + 1);
+        R.counts = counts_;
+        R.cursor = cursor_;
+        R.offsets = offsets_;
         // LDS plane size: a chunk spans at most two neighbouring tiles (serpentine
         // order), widened by the drift since the last sort (at most ~0.7 cell
         // per step in grid units) and the stencil halo (one cell below, two above)
-        ppt_ = gd.chunk_ppt > 0 ? gd.chunk_ppt : 8;
-        const int drift = sort_interval_ > 0 ? (7 * sort_interval_ + 9) / 10 : 0;
-        const int R = 2 * tile_r_ + 2 * drift + 3, C = 2 * tile_th_ + 2 * drift + 3;
-        lds_cap_ = sort_interval_ > 0 ? std::min(R * C, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
-        const int shm = (int)lds_push_bytes<T>(std::max(lds_cap_, 1));
-        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-        HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-        HIPCHK(hipStreamSynchronize(stream));
+        const int drift = sort_interval > 0 ? (7 * sort_interval + 9) / 10 : 0;
+        const int Rr = 2 * tile_r + 2 * drift + 3, Cc = 2 * tile_th + 2 * drift + 3;
+        R.lds_cap = sort_interval > 0 ? std::min(Rr * Cc, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
+        set_dep_scale();
+        R.inject = ph.inject && (ph.bg_kind == PIC_BG_MONOPOLE || ph.bg_kind == PIC_BG_DIPOLE);
+        R.kn = dkn_;
+        R.sn = dsn_;
+        R.Aj = dAj_;
+        R.rb0 = rb0_;
+        R.f_inj = ph.f_inj;
+        R.q_inj = ph.q_inj;
+        carry_ = dalloc<double>(nth + 1);
+        fill(carry_, (size_t)nth + 1, 0.0);
+        R.carry = carry_;
+        R.seed = ph.seed;
+        plan_.build({rd_}, ppt_, stream);
     }
+
+    const RunDev<T> &run_desc() const { return rd_; }
+    int ppt() const { return ppt_; }
 
     void inject(int64_t n, const double *x, const double *y, const double *ur, const double *ut, const double *up,
                 const double *w, const uint64_t *id) override
@@ -187,92 +517,75 @@ public:
             if (!(x[q] >= -lim && x[q] <= nr + lim && y[q] >= 0.0 && y[q] <= nth))
                 throw StatusError{PIC_EINVAL, "particle position outside the grid"};
         }
-        unsigned long long ntot = 0;
-        HIPCHK(hipMemcpyAsync(&ntot, ctr_ + kTotal, sizeof ntot, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        const unsigned long long ntot = c[kTotal];
+        const int cur = (int)c[kCur];
         if ((int64_t)ntot + n > cap_) throw StatusError{PIC_ECAPACITY, "particle capacity exceeded"};
         for (int64_t q = 0; q < n; ++q) qmax_ = std::max(qmax_, std::fabs(w[q]));
         const int64_t chunk = 1 << 22;
-        double *stage = dalloc_tmp<double>(6 * (size_t)std::min(n, chunk));
-        uint64_t *sid = id ? dalloc_tmp<uint64_t>((size_t)std::min(n, chunk)) : nullptr;
+        double *stage = dev_alloc<double>(6 * (size_t)std::min(n, chunk));
+        uint64_t *sid = id ? dev_alloc<uint64_t>((size_t)std::min(n, chunk)) : nullptr;
         std::vector<double> hb;
-        for (int64_t o = 0; o < n; o += chunk) {
-            const int64_t m = std::min(chunk, n - o);
-            hb.resize(6 * (size_t)m);
-            const double *srcs[6] = {x, y, ur, ut, up, w};
-            for (int a = 0; a < 6; ++a) std::memcpy(&hb[(size_t)a * m], srcs[a] + o, sizeof(double) * m);
-            HIPCHK(hipMemcpyAsync(stage, hb.data(), sizeof(double) * 6 * m, hipMemcpyHostToDevice, stream));
-            if (sid) HIPCHK(hipMemcpyAsync(sid, id + o, sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream));
-            const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
-            k_load<T><<<blocks, 256, 0, stream>>>(stage, sid, m, (long long)(ntot + o), nth, cell_[cur_],
-                                                  arr_[cur_][0], arr_[cur_][1], arr_[cur_][2], arr_[cur_][3],
-                                                  arr_[cur_][4], arr_[cur_][5], id_[cur_]);
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(stream));
+        try {
+            for (int64_t o = 0; o < n; o += chunk) {
+                const int64_t m = std::min(chunk, n - o);
+                hb.resize(6 * (size_t)m);
+                const double *srcs[6] = {x, y, ur, ut, up, w};
+                for (int a = 0; a < 6; ++a) std::memcpy(&hb[(size_t)a * m], srcs[a] + o, sizeof(double) * m);
+                HIPCHK(hipMemcpyAsync(stage, hb.data(), sizeof(double) * 6 * m, hipMemcpyHostToDevice, stream));
+                if (sid) HIPCHK(hipMemcpyAsync(sid, id + o, sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream));
+                const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
+                k_load<T><<<blocks, 256, 0, stream>>>(stage, sid, m, (long long)(ntot + o), nth, cell_[cur],
+                                                      arr_[cur][0], arr_[cur][1], arr_[cur][2], arr_[cur][3],
+                                                      arr_[cur][4], arr_[cur][5], id_[cur]);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(stream));
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(stage);
+            if (sid) (void)hipFree(sid);
+            throw;
         }
-        free_tmp(stage);
-        if (sid) free_tmp(sid);
-        const unsigned long long nn = ntot + n;
-        HIPCHK(hipMemcpyAsync(ctr_ + kTotal, &nn, sizeof nn, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        n_bound_ = (int64_t)nn;
-        need_sort_ = true;
+        HIPCHK(hipFree(stage));
+        if (sid) HIPCHK(hipFree(sid));
+        const unsigned long long upd[2] = {ntot + n, 1ull};
+        HIPCHK(hipMemcpyAsync(ctr_ + kTotal, &upd[0], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(ctr_ + kNeedSort, &upd[1], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (set_dep_scale()) {
+            plan_.upload({rd_}, stream);
+            ++version;
+        }
     }
 
     void step(int n) override
     {
-        if (timing) {
-            const size_t need = (size_t)n * kStages * 2;
-            while (evpool_.size() < need) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                evpool_.push_back(e);
-            }
-            std::fill(stage_used_, stage_used_ + (size_t)kStages, false);
-        }
-        for (int s = 0; s < n; ++s) {
-            ev_base_ = (size_t)s * kStages * 2;
-            one_step();
-        }
+        plan_.run(n, stream, timing ? &timer_ : nullptr);
         HIPCHK(hipStreamSynchronize(stream));
+        if (timing && n > 0) timer_.finish(n, stage_ms_);
+        raise_status(take_status(), "");
+    }
+
+    int take_status() override
+    {
         int st = 0;
-        HIPCHK(hipMemcpy(&st, status_, sizeof st, hipMemcpyDeviceToHost));
-        unsigned long long c[8];
-        HIPCHK(hipMemcpy(c, ctr_, sizeof c, hipMemcpyDeviceToHost));
-        n_bound_ = (int64_t)c[kTotal];
-        if (timing && n > 0) {
-            // mean device time per step of each stage over the steps of this call
-            for (int q = 0; q < kStages; ++q) {
-                stage_ms_[q] = 0.0;
-                if (!stage_used_[q]) continue;
-                for (int s = 0; s < n; ++s) {
-                    float ms = 0.f;
-                    const size_t b = (size_t)s * kStages * 2 + 2 * q;
-                    HIPCHK(hipEventElapsedTime(&ms, evpool_[b], evpool_[b + 1]));
-                    stage_ms_[q] += ms;
-                }
-                stage_ms_[q] /= n;
-            }
-        }
-        if (st & 1) {
+        HIPCHK(hipMemcpyAsync(&st, status_, sizeof st, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (st) {
             fill(status_, 1, 0);
-            throw StatusError{PIC_ECFL, "a particle moved one cell or more in one step (CFL)"};
+            HIPCHK(hipStreamSynchronize(stream));
         }
-        if (st & 2) {
-            fill(status_, 1, 0);
-            throw StatusError{PIC_ECAPACITY, "particle capacity exceeded by surface injection"};
-        }
-        if (st & 4) {
-            fill(status_, 1, 0);
-            throw StatusError{PIC_EDEVICE, "internal error: sort destination outside the particle store"};
-        }
+        return st;
     }
 
     void get_field(int comp, double *out) override
     {
         int32_t rows, cols, row0;
         field_shape(comp, &rows, &cols, &row0);
-        const T *src = comp < 6 ? fld_[comp] : fcur(comp - 6);
+        const T *src = comp < 6 ? fld_[comp] : rd_.ffin[comp - 6];
         std::vector<T> h(L.size());
         HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(T) * h.size(), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
@@ -294,20 +607,21 @@ public:
     int64_t get_particles(double *x, double *y, double *ur, double *ut, double *up, double *w, uint64_t *id,
                           int64_t cap) override
     {
-        unsigned long long ntot = 0;
-        HIPCHK(hipMemcpyAsync(&ntot, ctr_ + kTotal, sizeof ntot, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        const unsigned long long ntot = c[kTotal];
+        const int cur = (int)c[kCur];
         std::vector<uint32_t> hc(ntot);
-        HIPCHK(hipMemcpyAsync(hc.data(), cell_[cur_], sizeof(uint32_t) * ntot, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(hc.data(), cell_[cur], sizeof(uint32_t) * ntot, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         int64_t live = 0;
-        for (auto c : hc) live += c != kDead;
+        for (auto cl : hc) live += cl != kDead;
         if (live > cap) return -live;
         std::vector<T> ha(ntot);
         double *outs[6] = {x, y, ur, ut, up, w};
         for (int a = 0; a < 6; ++a) {
             if (!outs[a]) continue;
-            HIPCHK(hipMemcpyAsync(ha.data(), arr_[cur_][a], sizeof(T) * ntot, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipMemcpyAsync(ha.data(), arr_[cur][a], sizeof(T) * ntot, hipMemcpyDeviceToHost, stream));
             HIPCHK(hipStreamSynchronize(stream));
             int64_t m = 0;
             for (size_t q = 0; q < ntot; ++q) {
@@ -321,7 +635,7 @@ public:
         if (id) {
             std::vector<uint64_t> hi(ntot);
             if (with_ids_) {
-                HIPCHK(hipMemcpyAsync(hi.data(), id_[cur_], sizeof(uint64_t) * ntot, hipMemcpyDeviceToHost, stream));
+                HIPCHK(hipMemcpyAsync(hi.data(), id_[cur], sizeof(uint64_t) * ntot, hipMemcpyDeviceToHost, stream));
                 HIPCHK(hipStreamSynchronize(stream));
             }
             int64_t m = 0;
@@ -333,51 +647,58 @@ public:
 
     void counts(double *out) override
     {
-        unsigned long long c[8];
-        HIPCHK(hipMemcpyAsync(c, ctr_, sizeof c, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        unsigned long long c[kNumCounters];
+        read_counters(c);
         out[0] = (double)(c[kTotal] - c[kDeadSinceSort]);
         out[1] = (double)c[kInjected];
         out[2] = (double)c[kDeleted] + (double)c[kDeadSinceSort];
-        out[3] = (double)step_index;
+        out[3] = (double)c[kStep];
         out[4] = (double)c[kPartSteps];
     }
 
     void gauss(double *out) override
     {
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        const int cur = (int)c[kCur];
         const size_t fsz = L.size();
-        double *rho = dalloc_tmp<double>(fsz), *tmp = dalloc_tmp<double>(fsz);
-        double *G = dalloc_tmp<double>((size_t)(gd.nr + 1) * (gd.nth + 1));
-        fill(rho, fsz, 0.0);
-        fill(tmp, fsz, 0.0);
-        k_node_charge<T><<<2048, 256, 0, stream>>>(cell_[cur_], arr_[cur_][0], arr_[cur_][1], arr_[cur_][5],
-                                                   ctr_ + kTotal, L, rho);
-        HIPCHK(hipGetLastError());
-        double *a = rho, *b = tmp;
-        for (int pss = 0; pss < gd.n_filt; ++pss) {
-            FilterSet fs{};
-            fs.src[0] = a;
-            fs.dst[0] = b;
-            fs.kind[0] = 0;
-            fs.last_row[0] = gd.nr + L.G;
-            dim3 blk(64, 4), grd((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4, 1);
-            k_filter<double><<<grd, blk, 0, stream>>>(fs, L);
-            HIPCHK(hipGetLastError());
-            std::swap(a, b);
-        }
-        dim3 blk(64, 4), grd((gd.nth + 1 + 63) / 64, (gd.nr + 1 + 3) / 4);
-        k_gauss_flux<T><<<grd, blk, 0, stream>>>(fld_[cER], fld_[cETH], L, gA_r_, gdkb_, gA_t_, gsb_, G);
-        HIPCHK(hipGetLastError());
         const size_t N = (size_t)(gd.nr + 1) * (gd.nth + 1);
-        std::vector<double> hr(fsz);
-        HIPCHK(hipMemcpyAsync(out, G, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipMemcpyAsync(hr.data(), a, sizeof(double) * fsz, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        for (int i = 0; i <= gd.nr; ++i)
-            for (int j = 0; j <= gd.nth; ++j) out[N + (size_t)i * (gd.nth + 1) + j] = hr[L.at(i, j)];
-        free_tmp(rho);
-        free_tmp(tmp);
-        free_tmp(G);
+        double *rho = dev_alloc<double>(fsz);
+        double *tmp = nullptr, *G = nullptr;
+        try {
+            tmp = dev_alloc<double>(fsz);
+            G = dev_alloc<double>(N);
+            fill(rho, fsz, 0.0);
+            fill(tmp, fsz, 0.0);
+            k_node_charge<T><<<2048, 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1], arr_[cur][5],
+                                                       ctr_ + kTotal, L, rho);
+            HIPCHK(hipGetLastError());
+            double *a = rho, *b = tmp;
+            const dim3 blk(64, 4), fg((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4);
+            for (int pss = 0; pss < gd.n_filt; ++pss) {
+                k_filter_nodes<double><<<fg, blk, 0, stream>>>(a, b, L);
+                HIPCHK(hipGetLastError());
+                std::swap(a, b);
+            }
+            const dim3 grd((gd.nth + 1 + 63) / 64, (gd.nr + 1 + 3) / 4);
+            k_gauss_flux<T><<<grd, blk, 0, stream>>>(fld_[cER], fld_[cETH], L, gA_r_, gdkb_, gA_t_, gsb_, G);
+            HIPCHK(hipGetLastError());
+            std::vector<double> hr(fsz);
+            HIPCHK(hipMemcpyAsync(out, G, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipMemcpyAsync(hr.data(), a, sizeof(double) * fsz, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            for (int i = 0; i <= gd.nr; ++i)
+                for (int j = 0; j <= gd.nth; ++j) out[N + (size_t)i * (gd.nth + 1) + j] = hr[L.at(i, j)];
+        } catch (...) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(rho);
+            if (tmp) (void)hipFree(tmp);
+            if (G) (void)hipFree(G);
+            throw;
+        }
+        HIPCHK(hipFree(rho));
+        HIPCHK(hipFree(tmp));
+        HIPCHK(hipFree(G));
     }
 
     void get_carry(double *out) override
@@ -392,74 +713,72 @@ public:
         HIPCHK(hipStreamSynchronize(stream));
     }
 
+    void set_step(int64_t step) override
+    {
+        const unsigned long long v = (unsigned long long)step;
+        HIPCHK(hipMemcpyAsync(ctr_ + kStep, &v, sizeof v, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+
     void stage_ms(double *out) override { std::memcpy(out, stage_ms_, sizeof stage_ms_); }
 
 private:
-    int ppt_ = 8;
     static constexpr int kMaxLdsBytes = 64 * 1024;
-    enum { kTotal = 0, kDeadSinceSort = 1, kDeleted = 2, kInjected = 3, kLive = 4, kPartSteps = 5 };
 
     std::vector<void *> allocs_;
+    RunDev<T> rd_{};
+    Plan<T> plan_;
+    StageTimer timer_;
+    int ppt_ = 8;
     T *fld_[9] = {};
     T *ftmp_[3] = {};
-    bool f_in_tmp_ = false; // the filtered face charges of the last step live in ftmp_
     uint32_t *cell_[2] = {};
     T *arr_[2][6] = {};
     uint64_t *id_[2] = {};
-    int cur_ = 0;
     unsigned long long *ctr_ = nullptr;
     int *status_ = nullptr;
-    unsigned int *work_ = nullptr;
     double *carry_ = nullptr;
     unsigned int *counts_ = nullptr, *cursor_ = nullptr;
     unsigned long long *offsets_ = nullptr;
-    int ntr_ = 0, ntj_ = 0, n_keys_ = 0;
-    int tile_r_ = 8, tile_th_ = 8, sort_interval_ = 4;
-    int lds_cap_ = 0;
-    int64_t cap_ = 0, n_bound_ = 0;
+    int64_t cap_ = 0;
     double qmax_ = 0.0; // largest |w| held so far: sets the fixed-point deposit scale
-    bool with_ids_ = false, need_sort_ = true;
+    bool with_ids_ = false;
     Metric<T> m_{};
     const T *r_node_ = nullptr, *k_node_ = nullptr;
     const double *dkn_ = nullptr, *dsn_ = nullptr, *dAj_ = nullptr;
     const double *gA_r_ = nullptr, *gdkb_ = nullptr, *gA_t_ = nullptr, *gsb_ = nullptr;
     double rb0_ = 0.0;
-    static constexpr int kStages = 9; // sort, faraday, push, filter, ampere, absorb, inject, zero, total
-    std::vector<hipEvent_t> evpool_;
-    size_t ev_base_ = 0;
-    bool stage_used_[kStages] = {};
     double stage_ms_[kStages] = {};
 
     template <typename U>
     U *dalloc(size_t n)
     {
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(U) * std::max<size_t>(n, 1)) != hipSuccess)
-            throw StatusError{PIC_ENOMEM, "device allocation failed"};
+        U *p = dev_alloc<U>(n);
         allocs_.push_back(p);
-        return (U *)p;
-    }
-    template <typename U>
-    U *dalloc_tmp(size_t n)
-    {
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(U) * std::max<size_t>(n, 1)) != hipSuccess)
-            throw StatusError{PIC_ENOMEM, "device allocation failed"};
-        return (U *)p;
-    }
-    void free_tmp(void *p)
-    {
-        HIPCHK(hipStreamSynchronize(stream));
-        HIPCHK(hipFree(p));
+        return p;
     }
     template <typename U>
     void fill(U *p, size_t n, U v)
     {
-        const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
-        k_fill<U><<<std::max(blocks, 1), 256, 0, stream>>>(p, n, v);
-        HIPCHK(hipGetLastError());
+        dev_fill(p, n, v, stream);
     }
-    T *fcur(int c) const { return f_in_tmp_ ? ftmp_[c] : fld_[6 + c]; }
+    void read_counters(unsigned long long *c)
+    {
+        HIPCHK(hipMemcpyAsync(c, ctr_, sizeof(unsigned long long) * kNumCounters, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    // fixed-point scale of the LDS deposit from the largest |w| held;
+    // true when it changed
+    bool set_dep_scale()
+    {
+        const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
+        const T sc = (T)(std::ldexp(1.0, fixed_bits<T>()) / qm);
+        const T inv = (T)(qm * std::ldexp(1.0, -fixed_bits<T>()));
+        const bool changed = sc != rd_.dep_scale || inv != rd_.dep_inv;
+        rd_.dep_scale = sc;
+        rd_.dep_inv = inv;
+        return changed;
+    }
 
     template <typename U>
     const U *upload(const std::vector<double> &h)
@@ -569,212 +888,71 @@ private:
         gsb_ = upload<double>(sb);
     }
 
-    double inv_rl(double t) const
-    {
-        double om = ph.omega;
-        if (ph.t_spin > 0.0 && t < ph.t_spin) om = ph.omega * t / ph.t_spin;
-        return om / gd.c;
-    }
+};
 
-    Fields<T> fields() const
-    {
-        Fields<T> f;
-        for (int c = 0; c < 6; ++c) f.c[c] = fld_[c];
-        for (int c = 0; c < 3; ++c) f.c[6 + c] = fld_[6 + c];
-        return f;
-    }
-
-    void mark(int q, bool start)
-    {
-        if (!timing) return;
-        HIPCHK(hipEventRecord(evpool_[ev_base_ + 2 * q + (start ? 0 : 1)], stream));
-        stage_used_[q] = true;
-    }
-
-    void sort()
-    {
-        TileMap tm{L.G, tile_r_, tile_th_, ntj_, n_keys_};
-        fill(counts_, (size_t)n_keys_ + 1, 0u);
-        fill(cursor_, (size_t)n_keys_ + 1, 0u);
-        // one wave per span of kSortSpan particles (4 waves per block)
-        const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n_bound_ + 4 * kSortSpan - 1) / (4 * kSortSpan), 1),
-                                                  8192);
-        k_sort_hist<<<blocks, 256, 0, stream>>>(cell_[cur_], ctr_ + kTotal, tm, counts_);
-        HIPCHK(hipGetLastError());
-        k_sort_scan<<<1, 1024, 0, stream>>>(counts_, n_keys_, offsets_, ctr_ + kTotal, ctr_ + kLive);
-        HIPCHK(hipGetLastError());
-        SortArgs<T> sa{};
-        const int nxt = cur_ ^ 1;
-        sa.cell = cell_[cur_];
-        sa.cell_o = cell_[nxt];
-        for (int a = 0; a < 6; ++a) {
-            sa.a[a] = arr_[cur_][a];
-            sa.a_o[a] = arr_[nxt][a];
-        }
-        sa.id = id_[cur_];
-        sa.id_o = id_[nxt];
-        sa.n_total = ctr_ + kTotal;
-        sa.offsets = offsets_;
-        sa.cursor = cursor_;
-        sa.tm = tm;
-        sa.capacity = (unsigned long long)cap_;
-        sa.status = status_;
-        k_sort_scatter<T><<<blocks, 256, 0, stream>>>(sa);
-        HIPCHK(hipGetLastError());
-        k_finish_sort<<<1, 1, 0, stream>>>(ctr_);
-        HIPCHK(hipGetLastError());
-        cur_ = nxt;
-        need_sort_ = false;
-    }
-
-    void one_step()
-    {
-        mark(8, true);
-        const int nr = gd.nr, nth = gd.nth;
-        k_count_live<<<1, 1, 0, stream>>>(ctr_);
-        HIPCHK(hipGetLastError());
-        // sort
-        mark(0, true);
-        if (sort_interval_ > 0 && (need_sort_ || step_index % sort_interval_ == 0)) sort();
-        mark(0, false);
-        // zero the deposit planes
-        mark(7, true);
-        f_in_tmp_ = false;
-        for (int c = 0; c < 3; ++c) fill(fld_[6 + c], L.size(), (T)0);
-        mark(7, false);
-        const dim3 blk(64, 4), grd((nth + 1 + 63) / 64, (nr + 1 + 3) / 4);
-        const T hc = (T)(0.5 * gd.c);
-        mark(1, true);
-        k_faraday<T><<<grd, blk, 0, stream>>>(fields(), L, m_, hc);
-        HIPCHK(hipGetLastError());
-        mark(1, false);
-        // particles
-        mark(2, true);
-        push(inv_rl((double)step_index));
-        mark(2, false);
-        k_faraday<T><<<grd, blk, 0, stream>>>(fields(), L, m_, hc);
-        HIPCHK(hipGetLastError());
-        // filter
-        mark(3, true);
-        T *src[3] = {fld_[6], fld_[7], fld_[8]}, *dst[3] = {ftmp_[0], ftmp_[1], ftmp_[2]};
-        for (int pss = 0; pss < gd.n_filt; ++pss) {
-            FilterSet fs{};
-            for (int c = 0; c < 3; ++c) {
-                fs.src[c] = src[c];
-                fs.dst[c] = dst[c];
-                fs.kind[c] = c == 1 ? 1 : 0;
-                fs.last_row[c] = c == 0 ? nr + L.G - 1 : nr + L.G;
-            }
-            const dim3 fg((nth + 1 + 63) / 64, (L.rows() + 3) / 4, 3);
-            k_filter<T><<<fg, blk, 0, stream>>>(fs, L);
-            HIPCHK(hipGetLastError());
-            std::swap(src[0], dst[0]);
-            std::swap(src[1], dst[1]);
-            std::swap(src[2], dst[2]);
-        }
-        f_in_tmp_ = src[0] == ftmp_[0];
-        mark(3, false);
-        mark(4, true);
-        k_ampere<T><<<grd, blk, 0, stream>>>(fields(), src[0], src[1], src[2], L, m_, (T)gd.c);
-        HIPCHK(hipGetLastError());
-        mark(4, false);
-        mark(5, true);
-        if (gd.absorb_cells > 0) {
-            const int i0 = std::max(0, nr - gd.absorb_cells - 1);
-            const dim3 ag((nth + 1 + 63) / 64, (nr + 1 - i0 + 3) / 4);
-            k_absorb_b<T><<<ag, blk, 0, stream>>>(fields(), L, m_, i0);
-            HIPCHK(hipGetLastError());
-        }
-        mark(5, false);
-        mark(6, true);
-        if (ph.inject && (ph.bg_kind == PIC_BG_MONOPOLE || ph.bg_kind == PIC_BG_DIPOLE)) {
-            InjectArgs<T> a{};
-            a.L = L;
-            a.Er = fld_[cER];
-            a.bg = Background{ph.bg_kind, ph.B0, gd.r_in};
-            a.inv_rl = inv_rl((double)(step_index + 1));
-            a.rb0 = rb0_;
-            a.kn = dkn_;
-            a.sn = dsn_;
-            a.Aj = dAj_;
-            a.f_inj = ph.f_inj;
-            a.q_inj = ph.q_inj;
-            a.carry = carry_;
-            a.seed = ph.seed;
-            a.step = (uint64_t)step_index;
-            a.cell = cell_[cur_];
-            a.dx = arr_[cur_][0];
-            a.dy = arr_[cur_][1];
-            a.ur = arr_[cur_][2];
-            a.ut = arr_[cur_][3];
-            a.up = arr_[cur_][4];
-            a.w = arr_[cur_][5];
-            a.id = id_[cur_];
-            a.n_total = ctr_ + kTotal;
-            a.n_injected = ctr_ + kInjected;
-            a.capacity = cap_;
-            a.status = status_;
-            k_inject<T><<<1, 1024, 0, stream>>>(a);
-            HIPCHK(hipGetLastError());
-            // upper bound of the count for the next launch grids: every node
-            // can add at most f_inj |sigma| A / q + 1 pairs; the bound is only
-            // used to size grids, which loop over the device-side count
-            n_bound_ += 2 * (int64_t)(nth + 1) * 64;
-        }
-        mark(6, false);
-        mark(8, false);
-        ++step_index;
-    }
-
-    void push(double irl)
-    {
-        PushArgs<T> p{};
-        p.L = L;
-        p.f = fields();
-        p.bg = Background{ph.bg_kind, ph.B0, gd.r_in};
-        p.r_kind = gd.r_kind;
-        p.th_kind = gd.th_kind;
-        p.mover = gd.mover;
-        p.n_filt = gd.n_filt;
-        p.c = (T)gd.c;
-        p.dxi = (T)geo.dxi;
-        p.inv_dxi = (T)(1.0 / geo.dxi);
-        p.nth_f = (T)gd.nth;
-        p.two_over_nth = (T)(2.0 / gd.nth);
-        p.pi_over_nth = (T)(kPi / gd.nth);
-        p.inv_pi_over_nth = (T)(gd.nth / kPi);
-        p.eps0 = (T)(ph.q_over_m / (2.0 * gd.c));
-        p.inv_rl = (T)irl;
-        p.r_node = r_node_;
-        p.k_node = k_node_;
-        p.cell = cell_[cur_];
-        p.dx = arr_[cur_][0];
-        p.dy = arr_[cur_][1];
-        p.ur = arr_[cur_][2];
-        p.ut = arr_[cur_][3];
-        p.up = arr_[cur_][4];
-        p.w = arr_[cur_][5];
-        p.n_total = ctr_ + kTotal;
-        p.n_dead = ctr_ + kDeadSinceSort;
-        p.status = status_;
-        p.work = work_;
-        p.lds_cap = use_lds_ ? lds_cap_ : 0;
-        const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
-        p.dep_scale = (T)(std::ldexp(1.0, fixed_bits<T>()) / qm);
-        p.dep_inv = (T)(qm * std::ldexp(1.0, -fixed_bits<T>()));
-        fill(work_, 8, 0u);
-        const int CH = 256 * ppt_;
-        const int64_t nch = (n_bound_ + CH - 1) / CH;
-        const int grid = (int)std::max<int64_t>(8, std::min<int64_t>(8 * ((nch + 7) / 8), 8 * 256));
-        const size_t shm = p.lds_cap > 0 ? lds_push_bytes<T>(lds_cap_) : 0;
-        if (ppt_ == 4) k_push<T, 4><<<grid, 256, shm, stream>>>(p);
-        else if (ppt_ == 16) k_push<T, 16><<<grid, 256, shm, stream>>>(p);
-        else k_push<T, 8><<<grid, 256, shm, stream>>>(p);
-        HIPCHK(hipGetLastError());
-    }
-
+// Many runs of one precision stepped by one launch sequence.
+class Batch {
 public:
-    bool use_lds_ = true;
+    virtual ~Batch() {}
+    virtual void step(int n) = 0;
+    double last_ms = 0.0;
+};
+
+template <typename T>
+class BatchT final : public Batch {
+public:
+    BatchT(std::vector<EngineT<T> *> members, hipStream_t s) : members_(std::move(members)), stream_(s)
+    {
+        versions_.resize(members_.size());
+        HIPCHK(hipEventCreate(&ev_[0]));
+        HIPCHK(hipEventCreate(&ev_[1]));
+        plan_.build(collect(), members_[0]->ppt(), stream_);
+    }
+    ~BatchT() override
+    {
+        (void)hipEventDestroy(ev_[0]);
+        (void)hipEventDestroy(ev_[1]);
+    }
+
+    void step(int n) override
+    {
+        bool stale = false;
+        for (size_t r = 0; r < members_.size(); ++r) stale = stale || versions_[r] != members_[r]->version;
+        if (stale) plan_.upload(collect(), stream_);
+        HIPCHK(hipEventRecord(ev_[0], stream_));
+        plan_.run(n, stream_, nullptr);
+        HIPCHK(hipEventRecord(ev_[1], stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev_[0], ev_[1]));
+        last_ms = ms;
+        int first = -1, st = 0;
+        for (size_t r = 0; r < members_.size(); ++r) {
+            const int s = members_[r]->take_status();
+            if (s && first < 0) {
+                first = (int)r;
+                st = s;
+            }
+        }
+        if (first >= 0) raise_status(st, "run " + std::to_string(first) + ": ");
+    }
+
+private:
+    std::vector<EngineT<T> *> members_;
+    std::vector<unsigned> versions_;
+    hipStream_t stream_;
+    hipEvent_t ev_[2] = {};
+    Plan<T> plan_;
+
+    std::vector<RunDev<T>> collect()
+    {
+        std::vector<RunDev<T>> rd;
+        for (size_t r = 0; r < members_.size(); ++r) {
+            rd.push_back(members_[r]->run_desc());
+            versions_[r] = members_[r]->version;
+        }
+        return rd;
+    }
 };
 
 } // namespace
@@ -791,10 +969,18 @@ struct pic_ctx {
     std::string err;
 };
 
+struct pic_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Batch *impl = nullptr;
+    std::string err;
+};
+
 namespace {
 
-template <typename F>
-pic_status guarded(pic_ctx *ctx, F &&f)
+template <typename C, typename F>
+pic_status guarded(C *ctx, F &&f)
 {
     if (!ctx) return PIC_EINVAL;
     try {
@@ -817,6 +1003,14 @@ pic_status guarded(pic_ctx *ctx, F &&f)
 void need_engine(pic_ctx *ctx)
 {
     if (!ctx->eng) throw StatusError{PIC_ESTATE, "pic_init has not been called"};
+}
+
+template <typename T>
+Batch *make_batch(pic_ctx *const *runs, int n, hipStream_t s)
+{
+    std::vector<EngineT<T> *> m;
+    for (int r = 0; r < n; ++r) m.push_back(static_cast<EngineT<T> *>(runs[r]->eng));
+    return new BatchT<T>(std::move(m), s);
 }
 
 } // namespace
@@ -976,7 +1170,7 @@ pic_status pic_set_step_index(pic_ctx *ctx, int64_t step)
     return guarded(ctx, [&] {
         need_engine(ctx);
         if (step < 0) throw StatusError{PIC_EINVAL, "negative step index"};
-        ctx->eng->step_index = step;
+        ctx->eng->set_step(step);
     });
 }
 
@@ -1007,6 +1201,68 @@ void pic_destroy(pic_ctx *ctx)
     delete ctx->eng;
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+}
+
+pic_status pic_batch_create(pic_ctx *const *runs, int32_t n, void *hip_stream, pic_batch **out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    if (!runs || n < 1) return PIC_EINVAL;
+    for (int r = 0; r < n; ++r) {
+        if (!runs[r]) return PIC_EINVAL;
+        if (!runs[r]->eng) return PIC_ESTATE;
+        if (runs[r]->device != runs[0]->device || runs[r]->eng->gd.precision != runs[0]->eng->gd.precision)
+            return PIC_EINVAL;
+        for (int q = 0; q < r; ++q)
+            if (runs[q] == runs[r]) return PIC_EINVAL;
+    }
+    pic_batch *b = new pic_batch;
+    b->device = runs[0]->device;
+    const pic_status st = guarded(b, [&] {
+        if (hip_stream) {
+            b->stream = (hipStream_t)hip_stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        b->impl = runs[0]->eng->gd.precision == PIC_FP32 ? make_batch<float>(runs, n, b->stream)
+                                                         : make_batch<double>(runs, n, b->stream);
+    });
+    if (st != PIC_OK) {
+        if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+pic_status pic_batch_step(pic_batch *b, int32_t n_steps)
+{
+    return guarded(b, [&] {
+        if (n_steps < 0) throw StatusError{PIC_EINVAL, "negative step count"};
+        b->impl->step(n_steps);
+    });
+}
+
+pic_status pic_batch_elapsed_ms(pic_batch *b, double *ms)
+{
+    return guarded(b, [&] {
+        if (!ms) throw StatusError{PIC_EINVAL, "null output"};
+        *ms = b->impl->last_ms;
+    });
+}
+
+const char *pic_batch_last_error(const pic_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void pic_batch_destroy(pic_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b->impl;
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
 }
 
 } // extern "C"

@@ -1,0 +1,133 @@
+"""GPU batches: uneven runs stepped together by one launch sequence give, run
+by run, what the FP64 oracle gives for each run alone; the captured graph
+and the eagerly enqueued step agree; errors name their run."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1407_1810_amd import workloads as W
+from parity_util import TOL, compare_fields, compare_particles, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    from paper_1407_1810_amd.binding import gpu_available, lib
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    lib()
+
+
+def _uneven_runs():
+    """Three runs that differ in every per-run setting: grid, field kind,
+    filter passes, lossy layer, injection, tile and sort interval."""
+    out = []
+    specs = [
+        dict(nr=24, nth=20, pairs_per_cell=2, n_filt=3, absorb_cells=4, bg="monopole", omega_frac=0.3, inject=1,
+             seed=11, tile=(4, 4), si=2),
+        dict(nr=40, nth=32, pairs_per_cell=3, n_filt=0, absorb_cells=0, bg="dipole", omega_frac=0.2, inject=0,
+             seed=12, tile=(8, 8), si=3),
+        dict(nr=17, nth=44, pairs_per_cell=1, n_filt=2, absorb_cells=3, bg="dipole", omega_frac=0.25, inject=1,
+             seed=13, tile=(2, 8), si=-1),
+    ]
+    for sp in specs:
+        tile, si = sp.pop("tile"), sp.pop("si")
+        cfg = W.small_config(**sp)
+        p = dict(cfg["params"], q_inj=cfg["params"]["q_inj"] * 0.5, t_spin=4.0)
+        P = W.pair_plasma(p, cfg["pairs_per_cell"], 0.2, cfg["weight"], sp["seed"])
+        # unpair a quarter so that the plasma field is not zero
+        P["x"][1::4] = np.clip(P["x"][1::4] + 0.37, 0.0, p["nr"] - 1e-9)
+        out.append((p, P, tile, si))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_the_oracle_run_by_run(prec):
+    from paper_1407_1810_amd.binding import Batch
+    pairs = []
+    for p, P, tile, si in _uneven_runs():
+        o, s = make_pair(p, P, prec, capacity=1 << 18, tile=tile, sort_interval=si)
+        pairs.append((p, o, s))
+    b = Batch([s for _, _, s in pairs])
+    t = TOL[prec]
+    for k in range(6):
+        _say("batch", prec, "step", k)
+        b.step(1)
+        for r, (p, o, s) in enumerate(pairs):
+            o.step(1)
+            scale = 10.0 * (1.0 if prec == "fp32" else (k + 1))
+            compare_fields(o, s, t["field"] * scale)
+            compare_particles(o, s, {kk: v * scale for kk, v in t.items()}, p["nth"], t["band"] * scale)
+            assert s.counts()["step"] == k + 1
+    inj = [s.counts()["injected"] for _, _, s in pairs]
+    assert inj[0] > 0 and inj[2] > 0 and inj[1] == 0
+    for _, o, s in pairs:
+        assert s.counts()["injected"] == o.counters()[0]
+    assert b.elapsed_ms() > 0.0
+    b.close()
+
+
+def test_graph_and_eager_steps_agree():
+    """pic_step replays a captured graph; with stage timing on it enqueues
+    the same launches one by one.  Both give the same state."""
+    from paper_1407_1810_amd.binding import Sim
+    p, P, tile, si = _uneven_runs()[0]
+    sims = []
+    for timing in (False, True):
+        s = Sim(p, precision="fp64", capacity=1 << 18, tile=tile, sort_interval=si)
+        s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+        s.set_timing(timing)
+        s.step(7)
+        sims.append(s)
+    st = sims[1].stage_ms()
+    assert st["total"] > 0.0 and st["push"] > 0.0
+    compare_fields(sims[0], sims[1], 1e-12)
+    a, c = sims[0].particles(), sims[1].particles()
+    ka, kc = np.argsort(a["id"]), np.argsort(c["id"])
+    for k in ("x", "y", "ur", "ut", "up", "w"):
+        assert np.allclose(a[k][ka], c[k][kc], rtol=0, atol=1e-12 * (1 + np.abs(a[k]).max()))
+    assert sims[0].counts() == sims[1].counts()
+
+
+def test_batch_of_one_equals_the_context_alone():
+    from paper_1407_1810_amd.binding import Batch, Sim
+    p, P, tile, si = _uneven_runs()[1]
+    s1 = Sim(p, precision="fp32", capacity=1 << 18, tile=tile, sort_interval=si)
+    s2 = Sim(p, precision="fp32", capacity=1 << 18, tile=tile, sort_interval=si)
+    for s in (s1, s2):
+        s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+    b = Batch([s2])
+    s1.step(5)
+    b.step(5)
+    compare_fields(s1, s2, 1e-5)
+    assert s1.counts() == s2.counts()
+    # a member may still be stepped alone between batch steps
+    s2.step(1)
+    b.step(1)
+    assert s2.counts()["step"] == 7
+
+
+def test_batch_errors_name_the_run():
+    from paper_1407_1810_amd.binding import Batch, PicError, Sim
+    runs = _uneven_runs()
+    p0, P0, _, _ = runs[1]
+    p1, _, _, _ = runs[0]
+    ok = Sim(p0, precision="fp64", capacity=1 << 16)
+    ok.add_particles(P0["x"], P0["y"], P0["ur"], P0["ut"], P0["up"], P0["w"], P0["id"])
+    tight = Sim(dict(p1, q_inj=p1["q_inj"] * 1e-3), precision="fp64", capacity=16)
+    b = Batch([ok, tight])
+    with pytest.raises(PicError) as e:
+        b.step(3)
+    assert e.value.code == -4 and "run 1" in str(e.value)
+    # mixed precisions are refused
+    other = Sim(p0, precision="fp32", capacity=16)
+    with pytest.raises(PicError) as e:
+        Batch([ok, other])
+    assert e.value.code == -1
