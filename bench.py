@@ -66,6 +66,66 @@ def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt):
     return res
 
 
+def run_batched(n_runs, steps, warmup, tune_steps, seq):
+    """The uneven ensemble in FP32: every run autotuned (sort tile and
+    interval), then stepped together by one batch (one launch sequence per
+    step, replayed from a HIP graph) and, for comparison, one run after the
+    other with its own launches."""
+    from collections import Counter
+
+    from paper_1407_1810_amd import workloads as W
+    from paper_1407_1810_amd.binding import Batch, Sim
+    cfg = W.config(4)
+    runs = cfg["runs"][:n_runs]
+    sims, picks, n0 = [], Counter(), 0
+    t0 = time.perf_counter()
+    for d in runs:
+        p = d["params"]
+        P = W.pair_plasma(p, d["pairs_per_cell"], d["theta_T"], d["weight"], d["seed"])
+        n = len(P["x"])
+        n0 += n
+        # room for the surface injection of the tuning, warm-up and timed steps
+        # (sized to stay near half the preload over that window)
+        s = Sim(p, precision="fp32", capacity=2 * n + (4 << 20), ids=False)
+        s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"])
+        del P
+        best, _ = s.autotune(steps=tune_steps)
+        picks[f"{best[0]}x{best[1]}/K{best[2]}"] += 1
+        sims.append(s)
+    log(f"[batched] {len(sims)} runs, {n0} particles loaded and autotuned in {time.perf_counter() - t0:.1f} s: "
+        f"{dict(picks)}")
+    b = Batch(sims)
+    b.step(warmup)
+    ps0 = sum(s.counts()["particle_steps"] for s in sims)
+    t0 = time.perf_counter()
+    b.step(steps)
+    wall = time.perf_counter() - t0
+    dev_ms = b.elapsed_ms()
+    ps = sum(s.counts()["particle_steps"] for s in sims) - ps0
+    live = sum(s.counts()["live"] for s in sims)
+    res = dict(value=ps / wall, ms_per_step=1e3 * wall / steps, device_ms_per_step=dev_ms / steps,
+               particle_steps=ps, runs=len(sims), particles_start=n0, live_end=live, autotuned=dict(picks),
+               steps=steps, warmup=warmup)
+    log(f"[batched] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step")
+    if seq:
+        wall_s, ps_s = 0.0, 0
+        for s in sims:
+            c0 = s.counts()["particle_steps"]
+            t0 = time.perf_counter()
+            s.step(steps)
+            wall_s += time.perf_counter() - t0
+            ps_s += s.counts()["particle_steps"] - c0
+        res["sequential_value"] = ps_s / wall_s
+        res["sequential_ms_per_step"] = 1e3 * wall_s / steps
+        res["speedup_vs_sequential"] = res["value"] / res["sequential_value"]
+        log(f"[batched] sequential: {res['sequential_value']:.4e} particle-steps/s, "
+            f"batch speedup {res['speedup_vs_sequential']:.2f}x")
+    b.close()
+    for s in sims:
+        s.close()
+    return res
+
+
 def cpu_baseline(cfg, P, seconds=12.0, max_threads=16):
     """The FP64 oracle on the host cores, same workload, bounded sample:
     the full grid with every 4th pair of the particle set, as many steps as
@@ -108,6 +168,11 @@ def main():
     ap.add_argument("--tile", type=str, default="4x8")
     ap.add_argument("--sort-interval", type=int, default=8)
     ap.add_argument("--ppt", type=int, default=8, help="particles per thread of a push work-group (4, 8, 16)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-runs", type=int, default=64)
+    ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--batched-warmup", type=int, default=50)
+    ap.add_argument("--batched-tune-steps", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -137,6 +202,9 @@ def main():
     r64 = None
     if not args.no_fp64:
         r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, args.sort_interval, args.ppt)
+    rb = None
+    if not args.no_batched:
+        rb = run_batched(args.batched_runs, args.batched_steps, args.batched_warmup, args.batched_tune_steps, True)
     cells = p["nr"] * p["nth"]
     push_ms = r32["stage_ms"]["push"]
     bytes_launch = PUSH_BYTES["fp32"] * r32["mean_live"] + CELL_BYTES["fp32"] * cells
@@ -168,6 +236,7 @@ def main():
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
             "stage_ms": {k: round(v, 5) for k, v in r64["stage_ms"].items()},
             "fp32_speedup": r32["value"] / r64["value"]},
+        "batched_fp32": rb,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

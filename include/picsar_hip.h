@@ -146,7 +146,9 @@ pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, dou
 
 /* Moments and diagnostics:
  *  PIC_MOM_COUNTS: out[0..4] = live particles, injected total, deleted
- *                  total, step index, particle-steps advanced since init
+ *                  total, step index, particle-steps advanced since init;
+ *                  out[5] (if cap >= 6) = push chunks whose cells did not fit
+ *                  the LDS planes and went through global memory
  *  PIC_MOM_GAUSS:  Gauss diagnostic in FP64 (Sec. 2, App. B): out[0..N) =
  *                  closed-surface flux of E out of each dual cell,
  *                  out[N..2N) = the n_filt-filtered bilinear particle
@@ -168,6 +170,22 @@ pic_status pic_set_carry(pic_ctx *ctx, const double *carry, int64_t n);
 
 /* Turn per-stage device timing (HIP events on the context stream) on/off. */
 pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
+
+/* Change the counting-sort tile (tile_r x tile_th cells, each >= 1) and the
+ * steps between sorts (> 0, or < 0 for never) of a live context; the next
+ * step sorts.  Speed only: results change by float reordering at most.
+ * PIC_EINVAL for a zero interval or a tile side outside 1..4096. */
+pic_status pic_set_sort(pic_ctx *ctx, int32_t tile_r, int32_t tile_th, int32_t sort_interval);
+
+/* Per-run autotuning of the sort: for each of n_cand candidates
+ * cand[3q..3q+2] = (tile_r, tile_th, sort_interval) the context takes one
+ * step with it and then `steps` more (rounded up to whole sort periods),
+ * timed with HIP events; the candidate with the least device time per
+ * particle-step is kept and written to best[0..2], its time in ns per
+ * particle-step to *best_ns (may be NULL).  The tuning steps are real
+ * steps of the run (its state and step index advance). */
+pic_status pic_autotune(pic_ctx *ctx, const int32_t *cand, int32_t n_cand, int32_t steps, int32_t *best,
+                        double *best_ns);
 
 /* Message of the last failed call on ctx (empty if none). */
 const char *pic_last_error(const pic_ctx *ctx);
@@ -206,6 +224,14 @@ pic_status pic_batch_step(pic_batch *b, int32_t n_steps);
 /* Device time in ms of the last pic_batch_step, from HIP events on the
  * batch stream around its launches. */
 pic_status pic_batch_elapsed_ms(pic_batch *b, double *ms);
+
+/* Per-stage device timing of batch steps, as pic_set_timing /
+ * PIC_MOM_STAGE_MS for a context: with timing on the launches are enqueued
+ * one by one between HIP events instead of replaying the graph;
+ * pic_batch_stage_ms writes the 9 stage means of the last pic_batch_step
+ * (cap >= 9). */
+pic_status pic_batch_set_timing(pic_batch *b, int32_t on);
+pic_status pic_batch_stage_ms(pic_batch *b, double *out, int64_t cap);
 
 /* Message of the last failed call on b (empty if none). */
 const char *pic_batch_last_error(const pic_batch *b);

@@ -23,13 +23,17 @@ FLAG_IDS = 1
 MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS = 0, 1, 2, 3
 STAGES = ["sort", "faraday", "push", "filter", "ampere", "absorb", "inject", "zero", "total"]
 
+# (tile_r, tile_th, sort interval) tried by Sim.autotune by default
+AUTOTUNE_CANDIDATES = [(4, 8, 4), (4, 8, 8), (8, 8, 8), (4, 4, 4), (8, 16, 8), (4, 8, 16)]
+
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "PIC_ECAPACITY",
           -5: "PIC_ENAN", -6: "PIC_EDEVICE", -7: "PIC_ESTATE"}
 
 EXPORTED = ["pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
             "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
-            "pic_set_timing", "pic_last_error", "pic_destroy", "pic_batch_create", "pic_batch_step",
-            "pic_batch_elapsed_ms", "pic_batch_last_error", "pic_batch_destroy"]
+            "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_last_error", "pic_destroy",
+            "pic_batch_create", "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing",
+            "pic_batch_stage_ms", "pic_batch_last_error", "pic_batch_destroy"]
 
 
 class PicError(RuntimeError):
@@ -76,19 +80,24 @@ def lib():
         L.pic_set_step_index.argtypes = [vp, i64]
         L.pic_set_carry.argtypes = [vp, P(d), i64]
         L.pic_set_timing.argtypes = [vp, i32]
+        L.pic_set_sort.argtypes = [vp, i32, i32, i32]
+        L.pic_autotune.argtypes = [vp, P(i32), i32, i32, P(i32), P(d)]
         L.pic_last_error.argtypes = [vp]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [vp]
         L.pic_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
         L.pic_batch_step.argtypes = [vp, i32]
         L.pic_batch_elapsed_ms.argtypes = [vp, P(d)]
+        L.pic_batch_set_timing.argtypes = [vp, i32]
+        L.pic_batch_stage_ms.argtypes = [vp, P(d), i64]
         L.pic_batch_last_error.argtypes = [vp]
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [vp]
         for name in ("pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape",
                      "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_moments",
-                     "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_batch_create",
-                     "pic_batch_step", "pic_batch_elapsed_ms"):
+                     "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_set_sort", "pic_autotune",
+                     "pic_batch_create",
+                     "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing", "pic_batch_stage_ms"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -185,6 +194,21 @@ class Sim:
     def set_timing(self, on=True):
         self._check(lib().pic_set_timing(self._h, 1 if on else 0))
 
+    def set_sort(self, tile_r, tile_th, sort_interval):
+        self._check(lib().pic_set_sort(self._h, int(tile_r), int(tile_th), int(sort_interval)))
+
+    def autotune(self, candidates=None, steps=8):
+        """Pick the sort tile and interval with the least device time per
+        particle-step among `candidates` ((tile_r, tile_th, interval) tuples);
+        the tuning steps advance the run.  Returns (best, ns per particle-step)."""
+        cands = AUTOTUNE_CANDIDATES if candidates is None else [tuple(int(v) for v in c) for c in candidates]
+        flat = np.ascontiguousarray(np.array(cands, dtype=np.int32).reshape(-1))
+        best = np.zeros(3, dtype=np.int32)
+        ns = C.c_double()
+        self._check(lib().pic_autotune(self._h, flat.ctypes.data_as(C.POINTER(C.c_int32)), len(cands), int(steps),
+                                       best.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ns)))
+        return tuple(int(v) for v in best), ns.value
+
     # fields ------------------------------------------------------------------
     def shape(self, comp):
         c = COMPS.index(comp) if isinstance(comp, str) else int(comp)
@@ -206,10 +230,10 @@ class Sim:
 
     # moments -----------------------------------------------------------------
     def counts(self):
-        out = np.zeros(5)
-        self._check(lib().pic_get_moments(self._h, MOM_COUNTS, _dp(out), 5))
+        out = np.zeros(6)
+        self._check(lib().pic_get_moments(self._h, MOM_COUNTS, _dp(out), 6))
         return dict(live=int(out[0]), injected=int(out[1]), deleted=int(out[2]), step=int(out[3]),
-                    particle_steps=int(out[4]))
+                    particle_steps=int(out[4]), global_chunks=int(out[5]))
 
     def gauss(self):
         N = (self.nr + 1) * (self.nth + 1)
@@ -257,6 +281,14 @@ class Batch:
         out = C.c_double()
         self._check(lib().pic_batch_elapsed_ms(self._h, C.byref(out)))
         return out.value
+
+    def set_timing(self, on=True):
+        self._check(lib().pic_batch_set_timing(self._h, 1 if on else 0))
+
+    def stage_ms(self):
+        out = np.zeros(9)
+        self._check(lib().pic_batch_stage_ms(self._h, _dp(out), 9))
+        return dict(zip(STAGES, out.tolist()))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

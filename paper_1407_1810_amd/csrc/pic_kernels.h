@@ -68,6 +68,7 @@ enum : int {
     kCur = 7,           // current particle buffer (0 or 1)
     kNeedSort = 8,      // particles were appended since the last sort
     kSortNow = 9,       // the current step sorts
+    kGlobalChunks = 10, // push chunks whose cells did not fit the LDS planes
     kNumCounters = 16
 };
 
@@ -148,8 +149,17 @@ __device__ inline int run_of(const unsigned long long *__restrict__ off, int n_r
     return lo;
 }
 
-// (row, column) of thread (threadIdx.x, threadIdx.y) of a 64 x 4 block in
-// the local block lb of a run whose rows are `ncol` wide.
+// Field kernels use 64 x 4 work-groups; each thread takes kRowSteps
+// consecutive rows of one column, so a work-group covers 64 columns x
+// kBlockRows rows, the per-work-group run lookup is paid once per
+// kRowSteps cells of a thread, and a thread's loads of neighbouring rows
+// are shared and issued together.
+constexpr int kRowSteps = 8;
+constexpr int kBlockRows = 4 * kRowSteps;
+constexpr int kZeroPerThread = 16;
+
+// First (row, column) of thread (threadIdx.x, threadIdx.y) in the local
+// work-group lb of a run whose rows are `ncol` wide.
 struct Cell2 {
     int i, j;
 };
@@ -157,7 +167,7 @@ __device__ inline Cell2 block_cell(int lb, int ncol)
 {
     const int nbx = (ncol + 63) / 64;
     const int by = lb / nbx, bx = lb - by * nbx;
-    return Cell2{by * 4 + (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
+    return Cell2{by * kBlockRows + kRowSteps * (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
 }
 
 template <typename T>
@@ -222,7 +232,8 @@ __global__ void k_sort_finish(const RunDev<T> *__restrict__ runs, int n_runs, in
 // [off[r], off[r+1]) of the launch
 // ------------------------------------------------------------------
 
-// Clear the three deposit planes (256 threads x 4 entries per work-group).
+// Clear the three deposit planes (256 threads x kZeroPerThread entries per
+// work-group).
 template <typename T>
 __global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ runs, int n_runs,
                                                 const int *__restrict__ off)
@@ -230,14 +241,15 @@ __global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ ru
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
     const size_t n = R.L.size();
-    const size_t b = (size_t)(blockIdx.x - off[r]) * 1024 + threadIdx.x;
+    T *f0 = R.fld[cFR], *f1 = R.fld[cFTH], *f2 = R.fld[cFPH];
+    const size_t b = (size_t)(blockIdx.x - off[r]) * (256 * kZeroPerThread) + threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kZeroPerThread; ++q) {
         const size_t e = b + 256 * q;
         if (e < n) {
-            R.fld[cFR][e] = (T)0;
-            R.fld[cFTH][e] = (T)0;
-            R.fld[cFPH][e] = (T)0;
+            f0[e] = (T)0;
+            f1[e] = (T)0;
+            f2[e] = (T)0;
         }
     }
 }
@@ -254,23 +266,29 @@ __global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ r
     const Layout L = R.L;
     const int nr = L.nr, nth = L.nth;
     const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
-    const int i = q.i, j = q.j;
-    if (i > nr || j > nth) return;
-    const Metric<T> &m = R.m;
+    const int j = q.j;
+    if (j > nth) return;
+    const Metric<T> m = R.m;
     const T hc = hc_frac * R.c;
-    const T *Er = R.fld[cER], *Eth = R.fld[cETH], *Eph = R.fld[cEPH];
-    if (i >= 1 && i < nr && j < nth) {
-        const T circ = Eph[L.at(i, j)] * m.s[j] - Eph[L.at(i, j + 1)] * m.s[j + 1];
-        R.fld[cBR][L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
-    }
-    if (i < nr && j >= 1 && j < nth) {
-        const T circ = Eph[L.at(i + 1, j)] * m.r_node[i + 1 + L.G] - Eph[L.at(i, j)] * m.r_node[i + L.G];
-        R.fld[cBTH][L.at(i, j)] += hc * circ * m.idr2[i];
-    }
-    if (i < nr && j < nth) {
-        const T a = Eth[L.at(i, j)] * m.r_node[i + L.G] - Eth[L.at(i + 1, j)] * m.r_node[i + 1 + L.G];
-        const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * m.dr[i] * m.idth[j];
-        R.fld[cBPH][L.at(i, j)] += hc * (a - b) * m.idr2[i];
+    const T *__restrict__ Er = R.fld[cER], *__restrict__ Eth = R.fld[cETH], *__restrict__ Eph = R.fld[cEPH];
+    T *__restrict__ Br = R.fld[cBR], *__restrict__ Bth = R.fld[cBTH], *__restrict__ Bph = R.fld[cBPH];
+#pragma unroll
+    for (int rs = 0; rs < kRowSteps; ++rs) {
+        const int i = q.i + rs;
+        if (i > nr) break;
+        if (i >= 1 && i < nr && j < nth) {
+            const T circ = Eph[L.at(i, j)] * m.s[j] - Eph[L.at(i, j + 1)] * m.s[j + 1];
+            Br[L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
+        }
+        if (i < nr && j >= 1 && j < nth) {
+            const T circ = Eph[L.at(i + 1, j)] * m.r_node[i + 1 + L.G] - Eph[L.at(i, j)] * m.r_node[i + L.G];
+            Bth[L.at(i, j)] += hc * circ * m.idr2[i];
+        }
+        if (i < nr && j < nth) {
+            const T a = Eth[L.at(i, j)] * m.r_node[i + L.G] - Eth[L.at(i + 1, j)] * m.r_node[i + 1 + L.G];
+            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * m.dr[i] * m.idth[j];
+            Bph[L.at(i, j)] += hc * (a - b) * m.idr2[i];
+        }
     }
 }
 
@@ -284,28 +302,34 @@ __global__ __launch_bounds__(256) void k_ampere(const RunDev<T> *__restrict__ ru
     const Layout L = R.L;
     const int nr = L.nr, nth = L.nth;
     const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
-    const int i = q.i, j = q.j;
-    if (i > nr || j > nth) return;
-    const Metric<T> &m = R.m;
+    const int j = q.j;
+    if (j > nth) return;
+    const Metric<T> m = R.m;
     const T c = R.c;
-    const T *Br = R.fld[cBR], *Bth = R.fld[cBTH], *Bph = R.fld[cBPH];
-    const T *Fr = R.ffin[0], *Fth = R.ffin[1], *Fph = R.ffin[2];
-    if (i < nr) {
-        const T t1 = j < nth ? m.sb[j] * Bph[L.at(i, j)] : (T)0;
-        const T t0 = j > 0 ? m.sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
-        T &e = R.fld[cER][L.at(i, j)];
-        e = (e + (c * (t1 - t0) * m.invrb[i] - Fr[L.at(i, j)] * m.invA[i]) * m.idkb[j]) * m.ab_half[i];
-    }
-    if (i >= 1 && i < nr && j < nth) {
-        const T circ = m.rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - m.rb[i + L.G] * Bph[L.at(i, j)];
-        T &e = R.fld[cETH][L.at(i, j)];
-        e = (e + (c * circ - Fth[L.at(i, j)] * m.isb2pi[j]) * m.idrb2[i]) * m.ab_int[i];
-    }
-    if (i >= 1 && i < nr && j >= 1 && j < nth) {
-        const T a = m.rb[i + L.G] * Bth[L.at(i, j)] - m.rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
-        const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * m.drb[i] * m.idthb[j];
-        T &e = R.fld[cEPH][L.at(i, j)];
-        e = (e + (c * (a - b) - Fph[L.at(i, j)] * m.idthb[j]) * m.idrb2[i]) * m.ab_int[i];
+    const T *__restrict__ Br = R.fld[cBR], *__restrict__ Bth = R.fld[cBTH], *__restrict__ Bph = R.fld[cBPH];
+    const T *__restrict__ Fr = R.ffin[0], *__restrict__ Fth = R.ffin[1], *__restrict__ Fph = R.ffin[2];
+    T *__restrict__ Er = R.fld[cER], *__restrict__ Eth = R.fld[cETH], *__restrict__ Eph = R.fld[cEPH];
+#pragma unroll
+    for (int rs = 0; rs < kRowSteps; ++rs) {
+        const int i = q.i + rs;
+        if (i > nr) break;
+        if (i < nr) {
+            const T t1 = j < nth ? m.sb[j] * Bph[L.at(i, j)] : (T)0;
+            const T t0 = j > 0 ? m.sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
+            T &e = Er[L.at(i, j)];
+            e = (e + (c * (t1 - t0) * m.invrb[i] - Fr[L.at(i, j)] * m.invA[i]) * m.idkb[j]) * m.ab_half[i];
+        }
+        if (i >= 1 && i < nr && j < nth) {
+            const T circ = m.rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - m.rb[i + L.G] * Bph[L.at(i, j)];
+            T &e = Eth[L.at(i, j)];
+            e = (e + (c * circ - Fth[L.at(i, j)] * m.isb2pi[j]) * m.idrb2[i]) * m.ab_int[i];
+        }
+        if (i >= 1 && i < nr && j >= 1 && j < nth) {
+            const T a = m.rb[i + L.G] * Bth[L.at(i, j)] - m.rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
+            const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * m.drb[i] * m.idthb[j];
+            T &e = Eph[L.at(i, j)];
+            e = (e + (c * (a - b) - Fph[L.at(i, j)] * m.idthb[j]) * m.idrb2[i]) * m.ab_int[i];
+        }
     }
 }
 
@@ -319,13 +343,19 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
     const RunDev<T> &R = runs[r];
     const Layout L = R.L;
     const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
-    const int i = L.nr - R.absorb_cells - 1 + q.i, j = q.j;
-    if (i < 0 || i > L.nr || j > L.nth) return;
-    const Metric<T> &m = R.m;
-    if (j < L.nth) R.fld[cBR][L.at(i, j)] *= m.ab_int[i];
-    if (i < L.nr) {
-        R.fld[cBTH][L.at(i, j)] *= m.ab_half[i];
-        if (j < L.nth) R.fld[cBPH][L.at(i, j)] *= m.ab_half[i];
+    const int j = q.j;
+    if (j > L.nth) return;
+    const Metric<T> m = R.m;
+    T *Br = R.fld[cBR], *Bth = R.fld[cBTH], *Bph = R.fld[cBPH];
+    for (int rs = 0; rs < kRowSteps; ++rs) {
+        const int i = L.nr - R.absorb_cells - 1 + q.i + rs;
+        if (i > L.nr) return;
+        if (i < 0) continue;
+        if (j < L.nth) Br[L.at(i, j)] *= m.ab_int[i];
+        if (i < L.nr) {
+            Bth[L.at(i, j)] *= m.ab_half[i];
+            if (j < L.nth) Bph[L.at(i, j)] *= m.ab_half[i];
+        }
     }
 }
 
@@ -369,16 +399,30 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const int comp = blockIdx.y;
     const int kind = comp == 1 ? 1 : 0;
     const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
-    const int i = -L.G + q.i, j = q.j;
+    const int j = q.j;
     const int ncol = kind ? L.nth : L.nth + 1;
     const int last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
-    if (i > last || j >= ncol) return;
-    const T *a = (pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp];
-    T *dst = (pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp];
-    T v = (T)0.5 * theta_pass(a, L, i, j, kind);
-    if (i > -L.G) v += (T)0.25 * theta_pass(a, L, i - 1, j, kind);
-    if (i < last) v += (T)0.25 * theta_pass(a, L, i + 1, j, kind);
-    dst[L.at(i, j)] = v;
+    if (j >= ncol) return;
+    const T *__restrict__ a = (pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp];
+    T *__restrict__ dst = (pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp];
+    const int i0 = -L.G + q.i;
+    if (i0 > last) return;
+    // theta passes of rows i0 - 1 .. i0 + kRowSteps, zero outside [-G, last]
+    T tp[kRowSteps + 2];
+#pragma unroll
+    for (int rs = 0; rs < kRowSteps + 2; ++rs) {
+        const int i = i0 - 1 + rs;
+        tp[rs] = (i >= -L.G && i <= last) ? theta_pass(a, L, i, j, kind) : (T)0;
+    }
+#pragma unroll
+    for (int rs = 0; rs < kRowSteps; ++rs) {
+        const int i = i0 + rs;
+        if (i > last) break;
+        T v = (T)0.5 * tp[rs + 1];
+        v += (T)0.25 * tp[rs];
+        v += (T)0.25 * tp[rs + 2];
+        dst[L.at(i, j)] = v;
+    }
 }
 
 // The same pass on one integer-j array (the Gauss diagnostic's node charge).
@@ -876,6 +920,7 @@ __global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs
             }
             __syncthreads();
         } else {
+            if (tid == 0 && cap > 0) atomicAdd(R.ctr + kGlobalChunks, 1ull);
             const GlobalView<T> view{&p.f, p.L};
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1

@@ -122,18 +122,26 @@ public:
     Plan() = default;
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
-    ~Plan()
+    ~Plan() { reset(); }
+
+    void reset()
     {
         if (exec_) (void)hipGraphExecDestroy(exec_);
         if (graph_) (void)hipGraphDestroy(graph_);
         if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
         for (void *p : allocs_) (void)hipFree(p);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        cap_stream_ = nullptr;
+        allocs_.clear();
     }
 
-    // Work-group maps, grids and LDS size for these runs; the table itself
-    // is uploaded by upload().
+    // Work-group maps, grids and LDS size for these runs, and the table
+    // (rebuilding drops the captured graph).
     void build(const std::vector<RunDev<T>> &rd, int ppt, hipStream_t s)
     {
+        HIPCHK(hipStreamSynchronize(s));
+        reset();
         n_ = (int)rd.size();
         ppt_ = ppt;
         runs_ = alloc<RunDev<T>>(n_);
@@ -152,10 +160,10 @@ public:
             const RunDev<T> &R = rd[r];
             const int nbx = (R.L.nth + 1 + 63) / 64;
             const int cnt[kMaps] = {
-                nbx * ((R.L.nr + 1 + 3) / 4),
-                nbx * ((R.L.rows() + 3) / 4),
-                R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + 3) / 4) : 0,
-                (int)((R.L.size() + 1023) / 1024),
+                nbx * ((R.L.nr + 1 + kBlockRows - 1) / kBlockRows),
+                nbx * ((R.L.rows() + kBlockRows - 1) / kBlockRows),
+                R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + kBlockRows - 1) / kBlockRows) : 0,
+                (int)((R.L.size() + 256 * kZeroPerThread - 1) / (256 * kZeroPerThread)),
                 R.sort_interval > 0 ? (R.tm.n_keys + 1 + 255) / 256 : 0,
             };
             for (int m = 0; m < kMaps; ++m) {
@@ -358,6 +366,9 @@ public:
     virtual void set_carry(const double *in) = 0;
     virtual void set_step(int64_t step) = 0;
     virtual void stage_ms(double *out) = 0;
+    virtual void set_sort(int tile_r, int tile_th, int sort_interval) = 0;
+    virtual void get_sort(int32_t *out) const = 0;
+    virtual double timed_steps(int n, double *psteps) = 0;
     // device status bits of the run (cleared on read)
     virtual int take_status() = 0;
 
@@ -393,7 +404,10 @@ class EngineT final : public Engine {
 public:
     ~EngineT() override
     {
+        plan_.reset();
         for (void *p : allocs_) (void)hipFree(p);
+        for (auto e : tev_)
+            if (e) (void)hipEventDestroy(e);
     }
 
     void init() override
@@ -411,9 +425,6 @@ public:
         geo.r_in = gd.r_in;
         geo.r_out = gd.r_out;
         geo.dxi = gd.r_kind == PIC_R_LOG ? std::log(gd.r_out / gd.r_in) / nr : (gd.r_out - gd.r_in) / nr;
-        const int tile_r = gd.tile_r > 0 ? gd.tile_r : 8;
-        const int tile_th = gd.tile_th > 0 ? gd.tile_th : 8;
-        const int sort_interval = gd.sort_interval == 0 ? 4 : gd.sort_interval;
         cap_ = gd.particle_capacity;
         if (ph.inject) qmax_ = std::fabs(ph.q_inj);
         with_ids_ = (gd.flags & PIC_FLAG_IDS) != 0;
@@ -472,23 +483,8 @@ public:
         status_ = dalloc<int>(1);
         fill(status_, 1, 0);
         R.status = status_;
-        // sort tiles over rows -G..nr+G
-        const int ntr = (L.rows() + tile_r - 1) / tile_r;
-        const int ntj = (nth + tile_th - 1) / tile_th;
-        R.tm = TileMap{L.G, tile_r, tile_th, ntj, ntr * ntj};
-        R.sort_interval = sort_interval;
-        counts_ = dalloc<unsigned int>(R.tm.n_keys + 1);
-        cursor_ = dalloc<unsigned int>(R.tm.n_keys + 1);
-        offsets_ = dalloc<unsigned long long>(R.tm.n_keys + 1);
-        R.counts = counts_;
-        R.cursor = cursor_;
-        R.offsets = offsets_;
-        // LDS plane size: a chunk spans at most two neighbouring tiles (serpentine
-        // order), widened by the drift since the last sort (at most ~0.7 cell
-        // per step in grid units) and the stencil halo (one cell below, two above)
-        const int drift = sort_interval > 0 ? (7 * sort_interval + 9) / 10 : 0;
-        const int Rr = 2 * tile_r + 2 * drift + 3, Cc = 2 * tile_th + 2 * drift + 3;
-        R.lds_cap = sort_interval > 0 ? std::min(Rr * Cc, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
+        sort_state(gd.tile_r > 0 ? gd.tile_r : 8, gd.tile_th > 0 ? gd.tile_th : 8,
+                   gd.sort_interval == 0 ? 4 : gd.sort_interval);
         set_dep_scale();
         R.inject = ph.inject && (ph.bg_kind == PIC_BG_MONOPOLE || ph.bg_kind == PIC_BG_DIPOLE);
         R.kn = dkn_;
@@ -654,6 +650,7 @@ public:
         out[2] = (double)c[kDeleted] + (double)c[kDeadSinceSort];
         out[3] = (double)c[kStep];
         out[4] = (double)c[kPartSteps];
+        out[5] = (double)c[kGlobalChunks];
     }
 
     void gauss(double *out) override
@@ -722,8 +719,75 @@ public:
 
     void stage_ms(double *out) override { std::memcpy(out, stage_ms_, sizeof stage_ms_); }
 
+    // New sort tile and interval for a live run: new key arrays and LDS
+    // plane size, a sort at the next step, a new launch plan.
+    void set_sort(int tile_r, int tile_th, int sort_interval) override
+    {
+        HIPCHK(hipStreamSynchronize(stream));
+        sort_state(tile_r, tile_th, sort_interval);
+        fill(ctr_ + kNeedSort, 1, 1ull);
+        plan_.build({rd_}, ppt_, stream);
+        ++version;
+    }
+
+    void get_sort(int32_t *out) const override
+    {
+        out[0] = rd_.tm.tile_r;
+        out[1] = rd_.tm.tile_th;
+        out[2] = rd_.sort_interval;
+    }
+
+    // n steps replayed from the graph; device time in ms between HIP events
+    // around them, and the particle-steps they advanced
+    double timed_steps(int n, double *psteps) override
+    {
+        if (!tev_[0]) {
+            HIPCHK(hipEventCreate(&tev_[0]));
+            HIPCHK(hipEventCreate(&tev_[1]));
+        }
+        unsigned long long c0[kNumCounters], c1[kNumCounters];
+        read_counters(c0);
+        HIPCHK(hipEventRecord(tev_[0], stream));
+        plan_.run(n, stream, nullptr);
+        HIPCHK(hipEventRecord(tev_[1], stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        raise_status(take_status(), "");
+        read_counters(c1);
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, tev_[0], tev_[1]));
+        if (psteps) *psteps = (double)(c1[kPartSteps] - c0[kPartSteps]);
+        return ms;
+    }
+
 private:
-    static constexpr int kMaxLdsBytes = 64 * 1024;
+    hipEvent_t tev_[2] = {};
+
+    void sort_state(int tile_r, int tile_th, int sort_interval)
+    {
+        RunDev<T> &R = rd_;
+        for (void *p : {(void *)counts_, (void *)cursor_, (void *)offsets_}) dfree(p);
+        // sort tiles over rows -G..nr+G
+        const int ntr = (L.rows() + tile_r - 1) / tile_r;
+        const int ntj = (L.nth + tile_th - 1) / tile_th;
+        R.tm = TileMap{L.G, tile_r, tile_th, ntj, ntr * ntj};
+        R.sort_interval = sort_interval;
+        counts_ = dalloc<unsigned int>(R.tm.n_keys + 1);
+        cursor_ = dalloc<unsigned int>(R.tm.n_keys + 1);
+        offsets_ = dalloc<unsigned long long>(R.tm.n_keys + 1);
+        R.counts = counts_;
+        R.cursor = cursor_;
+        R.offsets = offsets_;
+        // LDS plane size: a chunk spans at most two neighbouring tiles (serpentine
+        // order), widened by the drift since the last sort (at most ~0.7 cell
+        // per step in grid units) and the stencil halo (one cell below, two above)
+        const int drift = sort_interval > 0 ? (7 * sort_interval + 9) / 10 : 0;
+        const int Rr = 2 * tile_r + 2 * drift + 3, Cc = 2 * tile_th + 2 * drift + 3;
+        R.lds_cap = sort_interval > 0 ? std::min(Rr * Cc, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
+    }
+
+    // LDS of one push work-group: FP32 keeps four work-groups per CU (160 KB),
+    // FP64 is held at two per CU by its registers anyway
+    static constexpr int kMaxLdsBytes = sizeof(T) == 4 ? 40 * 1024 : 64 * 1024;
 
     std::vector<void *> allocs_;
     RunDev<T> rd_{};
@@ -756,6 +820,15 @@ private:
         U *p = dev_alloc<U>(n);
         allocs_.push_back(p);
         return p;
+    }
+    void dfree(void *p)
+    {
+        if (!p) return;
+        auto it = std::find(allocs_.begin(), allocs_.end(), p);
+        if (it != allocs_.end()) {
+            allocs_.erase(it);
+            HIPCHK(hipFree(p));
+        }
     }
     template <typename U>
     void fill(U *p, size_t n, U v)
@@ -896,6 +969,8 @@ public:
     virtual ~Batch() {}
     virtual void step(int n) = 0;
     double last_ms = 0.0;
+    bool timing = false;
+    double stage_ms[kStages] = {};
 };
 
 template <typename T>
@@ -918,14 +993,15 @@ public:
     {
         bool stale = false;
         for (size_t r = 0; r < members_.size(); ++r) stale = stale || versions_[r] != members_[r]->version;
-        if (stale) plan_.upload(collect(), stream_);
+        if (stale) plan_.build(collect(), members_[0]->ppt(), stream_);
         HIPCHK(hipEventRecord(ev_[0], stream_));
-        plan_.run(n, stream_, nullptr);
+        plan_.run(n, stream_, timing ? &timer_ : nullptr);
         HIPCHK(hipEventRecord(ev_[1], stream_));
         HIPCHK(hipStreamSynchronize(stream_));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ev_[0], ev_[1]));
         last_ms = ms;
+        if (timing && n > 0) timer_.finish(n, stage_ms);
         int first = -1, st = 0;
         for (size_t r = 0; r < members_.size(); ++r) {
             const int s = members_[r]->take_status();
@@ -943,6 +1019,7 @@ private:
     hipStream_t stream_;
     hipEvent_t ev_[2] = {};
     Plan<T> plan_;
+    StageTimer timer_;
 
     std::vector<RunDev<T>> collect()
     {
@@ -1143,10 +1220,13 @@ pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap)
         if (!out) throw StatusError{PIC_EINVAL, "null output"};
         const int64_t N = (int64_t)(ctx->eng->gd.nr + 1) * (ctx->eng->gd.nth + 1);
         switch (kind) {
-        case PIC_MOM_COUNTS:
+        case PIC_MOM_COUNTS: {
             if (cap < 5) throw StatusError{PIC_EINVAL, "output buffer too small"};
-            ctx->eng->counts(out);
+            double c[6];
+            ctx->eng->counts(c);
+            std::memcpy(out, c, sizeof(double) * (size_t)std::min<int64_t>(cap, 6));
             break;
+        }
         case PIC_MOM_GAUSS:
             if (cap < 2 * N) throw StatusError{PIC_EINVAL, "output buffer too small"};
             ctx->eng->gauss(out);
@@ -1188,6 +1268,53 @@ pic_status pic_set_timing(pic_ctx *ctx, int32_t on)
     return guarded(ctx, [&] {
         need_engine(ctx);
         ctx->eng->timing = on != 0;
+    });
+}
+
+pic_status pic_set_sort(pic_ctx *ctx, int32_t tile_r, int32_t tile_th, int32_t sort_interval)
+{
+    return guarded(ctx, [&] {
+        need_engine(ctx);
+        if (tile_r < 1 || tile_th < 1 || tile_r > 4096 || tile_th > 4096 || sort_interval == 0)
+            throw StatusError{PIC_EINVAL, "invalid sort tile or interval"};
+        ctx->eng->set_sort(tile_r, tile_th, sort_interval);
+    });
+}
+
+pic_status pic_autotune(pic_ctx *ctx, const int32_t *cand, int32_t n_cand, int32_t steps, int32_t *best,
+                        double *best_ns)
+{
+    return guarded(ctx, [&] {
+        need_engine(ctx);
+        if (!cand || n_cand < 1 || steps < 1 || !best) throw StatusError{PIC_EINVAL, "invalid autotune arguments"};
+        for (int q = 0; q < n_cand; ++q) {
+            const int32_t *c = cand + 3 * q;
+            if (c[0] < 1 || c[1] < 1 || c[0] > 4096 || c[1] > 4096 || c[2] == 0)
+                throw StatusError{PIC_EINVAL, "invalid autotune candidate"};
+        }
+        Engine *e = ctx->eng;
+        int bq = 0;
+        double bcost = 0.0;
+        for (int q = 0; q < n_cand; ++q) {
+            const int32_t *c = cand + 3 * q;
+            e->set_sort(c[0], c[1], c[2]);
+            e->timed_steps(1, nullptr); // sorts with the new tiles, captures the graph
+            // whole sort periods, so that every candidate pays its sorts
+            const int n = c[2] > 0 ? c[2] * ((steps + c[2] - 1) / c[2]) : steps;
+            double ps = 0.0;
+            const double ms = e->timed_steps(n, &ps);
+            const double cost = 1e6 * ms / std::max(ps, 1.0);
+            if (q == 0 || cost < bcost) {
+                bq = q;
+                bcost = cost;
+            }
+        }
+        const int32_t *c = cand + 3 * bq;
+        e->set_sort(c[0], c[1], c[2]);
+        best[0] = c[0];
+        best[1] = c[1];
+        best[2] = c[2];
+        if (best_ns) *best_ns = bcost;
     });
 }
 
@@ -1250,6 +1377,19 @@ pic_status pic_batch_elapsed_ms(pic_batch *b, double *ms)
     return guarded(b, [&] {
         if (!ms) throw StatusError{PIC_EINVAL, "null output"};
         *ms = b->impl->last_ms;
+    });
+}
+
+pic_status pic_batch_set_timing(pic_batch *b, int32_t on)
+{
+    return guarded(b, [&] { b->impl->timing = on != 0; });
+}
+
+pic_status pic_batch_stage_ms(pic_batch *b, double *out, int64_t cap)
+{
+    return guarded(b, [&] {
+        if (!out || cap < kStages) throw StatusError{PIC_EINVAL, "output buffer too small"};
+        std::memcpy(out, b->impl->stage_ms, sizeof(double) * kStages);
     });
 }
 

@@ -183,10 +183,24 @@ def config(k: int) -> dict:
     raise KeyError(k)
 
 
-def batched_runs(n_runs: int = 64, seed: int = 0):
+def injection_scale_estimate(p: dict, q: float, window: int) -> float:
+    """Order-of-magnitude count of macro-particles a rotator releases from
+    its surface over `window` steps with macro-charge q: the surface charge
+    scale B0 r_in Omega / c over the sphere 4 pi r_in^2, with Omega rising
+    linearly over t_spin.  Used only to size workloads."""
+    n1 = 4.0 * np.pi * p["B0"] * p["r_in"] ** 3 * p["omega"] / (p["c"] * q)
+    ts = p["t_spin"]
+    ramp = window - window * window / (2.0 * ts) if window < ts else window - 0.5 * ts
+    return float(n1 * ramp)
+
+
+def batched_runs(n_runs: int = 64, seed: int = 0, window: int = 350):
     """Uneven rotator runs: square grids 128..512 (steps of 64), Omega in
     [0.1, 0.5] c/R*, r in [1, 4 R_LC], 16..64 particles per cell, monopole and
-    dipole alternating; the run index is its seed."""
+    dipole alternating; the run index is its seed.  The injected macro-charge
+    of each run is raised (never lowered below the plasma weight) until the
+    surface-charge estimate over `window` steps is half the preloaded count,
+    so that every run stays a preloaded run with injection on top."""
     rng = np.random.Generator(np.random.Philox(seed + 12345))
     runs = []
     for k in range(n_runs):
@@ -196,6 +210,10 @@ def batched_runs(n_runs: int = 64, seed: int = 0):
         ppc = int(rng.choice([16, 32, 48, 64]))
         bg = "monopole" if k % 2 == 0 else "dipole"
         d = _rotator(n, n, bg, ppc // 2, 0, r_ratio=4.0 * r_lc, r_lc_over_rin=r_lc, seed=k)
+        p = d["params"]
+        n0 = p["nr"] * p["nth"] * 2 * d["pairs_per_cell"]
+        scale = max(1.0, injection_scale_estimate(p, d["weight"], window) / (0.5 * n0))
+        p["q_inj"] = d["weight"] * scale
         d["name"] = f"run{k}_{bg}_{n}x{n}_ppc{ppc}"
         runs.append(d)
     return runs

@@ -131,3 +131,35 @@ def test_batch_errors_name_the_run():
     with pytest.raises(PicError) as e:
         Batch([ok, other])
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_and_resort_keep_parity(prec):
+    """Retiling a live run (pic_set_sort) and autotuning it (which steps it
+    under every candidate) leave the trajectory the oracle's; a batch whose
+    member was retiled rebuilds its launch plan."""
+    from paper_1407_1810_amd.binding import Batch
+    runs = _uneven_runs()
+    (p0, P0, t0, k0), (p1, P1, t1, k1) = runs[0], runs[1]
+    o0, s0 = make_pair(p0, P0, prec, capacity=1 << 18, tile=t0, sort_interval=k0)
+    o1, s1 = make_pair(p1, P1, prec, capacity=1 << 18, tile=t1, sort_interval=k1)
+    t = TOL[prec]
+    best, ns = s0.autotune([(4, 8, 2), (2, 2, 1), (8, 4, 3)], steps=2)
+    assert best in [(4, 8, 2), (2, 2, 1), (8, 4, 3)] and ns > 0
+    n0 = s0.counts()["step"]
+    _say("autotune", prec, best, ns, "steps", n0)
+    assert n0 == (1 + 2) + (1 + 2) + (1 + 3)
+    o0.step(n0)
+    sc = 20.0 if prec == "fp32" else 10.0 * n0
+    compare_fields(o0, s0, t["field"] * sc)
+    compare_particles(o0, s0, {kk: v * sc for kk, v in t.items()}, p0["nth"], t["band"] * sc)
+    b = Batch([s0, s1])
+    b.step(2)
+    s1.set_sort(2, 16, 1)
+    b.step(2)
+    o0.step(4)
+    o1.step(4)
+    sc = 20.0 if prec == "fp32" else 10.0 * (n0 + 4)
+    for p, o, s in ((p0, o0, s0), (p1, o1, s1)):
+        compare_fields(o, s, t["field"] * sc)
+        compare_particles(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
