@@ -39,6 +39,37 @@ struct Fields {
     T *c[9];
 };
 
+// Pointers into device memory.  Pointers that kernels read from a table in
+// memory are generic to the compiler, which then emits FLAT instructions
+// (slower waits, no scalar base); cast to the global address space they
+// give global_* loads, stores and atomics.
+template <typename U>
+using gptr = __attribute__((address_space(1))) U *;
+template <typename U>
+__device__ __forceinline__ gptr<U> glb(U *p)
+{
+    return (gptr<U>)p;
+}
+template <typename U>
+__device__ __forceinline__ void atomic_add(gptr<U> p, U v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U>
+__device__ __forceinline__ U atomic_add_fetch_old(gptr<U> p, U v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_or(gptr<int> p, int v)
+{
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+struct GFields {
+    gptr<T> c[9];
+};
+
 // ---------------------------------------------------------------------
 // Math policy.  FP32: hardware reciprocal, reciprocal square root and
 // square root (1 ulp), exp via v_exp_f32, and short series for the small
@@ -56,6 +87,12 @@ struct FM<float> {
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    // sqrt(x) and 1/sqrt(x) of x > 0 from one hardware reciprocal square root
+    static __device__ __forceinline__ void sqrt_rsqrt(float x, float &s, float &is)
+    {
+        is = __builtin_amdgcn_rsqf(x);
+        s = x * is;
+    }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
     // log(1 + e): alternating series through e^8 for |e| < 1/32 (truncation < e^9 / 9)
     static __device__ __forceinline__ float log1p(float e)
@@ -94,6 +131,11 @@ struct FM<double> {
     static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ void sqrt_rsqrt(double x, double &s, double &is)
+    {
+        s = ::sqrt(x);
+        is = 1.0 / s;
+    }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
     static __device__ __forceinline__ double log1p(double e) { return ::log1p(e); }
     static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
@@ -106,56 +148,70 @@ struct Background {
     double B0, r0;     // surface field and conductor radius
 };
 
+// The increments are formed in scalars and added once at the end, so that
+// the compiler keeps E and B in registers whatever the case.
 template <typename T>
-__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T k, T s, T E[3],
+__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T ir, T k, T s, T E[3],
                                       T B[3])
 {
     const T B0 = (T)bg.B0, r0 = (T)bg.r0;
+    T e0 = (T)0, e1 = (T)0, b0 = (T)0, b1 = (T)0;
     switch (bg.kind) {
     case 1: // uniform B along the axis
-        B[0] += B0 * k;
-        B[1] -= B0 * s;
+        b0 = B0 * k;
+        b1 = -(B0 * s);
         break;
     case 2: { // monopole: inside corotation, outside the vacuum l = 1 field
-        const T q = r0 * FM<T>::rcp(r);
-        B[0] += B0 * q * q;
+        const T q = r0 * ir;
+        b0 = B0 * q * q;
         if (inside) {
-            E[1] -= B0 * r0 * q * s * inv_rl;
+            e1 = -(B0 * r0 * q * s * inv_rl);
         } else {
             const T a = B0 * r0 * q * q * q * inv_rl;
-            E[0] -= (T)2 * a * k;
-            E[1] -= a * s;
+            e0 = -((T)2 * a * k);
+            e1 = -(a * s);
         }
         break;
     }
     case 3:
     case 4: { // dipole; corotation inside (or everywhere for the drift test), l = 2 vacuum outside
-        const T q = r0 * FM<T>::rcp(r);
+        const T q = r0 * ir;
         const T q3 = q * q * q;
-        B[0] += (T)2 * B0 * q3 * k;
-        B[1] += B0 * q3 * s;
+        b0 = (T)2 * B0 * q3 * k;
+        b1 = B0 * q3 * s;
         if (inside || bg.kind == 4) {
             const T a = B0 * r0 * q * q * inv_rl;
-            E[0] += a * s * s;
-            E[1] -= (T)2 * a * s * k;
+            e0 = a * s * s;
+            e1 = -((T)2 * a * s * k);
         } else {
             const T a = (T)2 * B0 * r0 * q3 * q * inv_rl;
-            E[0] -= a * (T)0.5 * ((T)3 * k * k - (T)1);
-            E[1] -= a * s * k;
+            e0 = -(a * (T)0.5 * ((T)3 * k * k - (T)1));
+            e1 = -(a * s * k);
         }
         break;
     }
     default:
         break;
     }
+    E[0] += e0;
+    E[1] += e1;
+    B[0] += b0;
+    B[1] += b1;
+}
+
+template <typename T>
+__device__ inline void add_background(const Background &bg, T inv_rl, bool inside, T r, T k, T s, T E[3], T B[3])
+{
+    add_background(bg, inv_rl, inside, r, FM<T>::rcp(r), k, s, E, B);
 }
 
 // ---------------------------------------------------------------------
 // Movers (Cartesian).  u = gamma v / c, eps = q dt / (2 m c).
 // ---------------------------------------------------------------------
 
+// Returns 1 / gamma of the new momentum.
 template <typename T>
-__device__ inline void vay_push(T u[3], const T E[3], const T B[3], T eps)
+__device__ inline T vay_push(T u[3], const T E[3], const T B[3], T eps)
 {
     const T ig = FM<T>::rsqrt((T)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const T vx = u[0] * ig, vy = u[1] * ig, vz = u[2] * ig;
@@ -175,6 +231,7 @@ __device__ inline void vay_push(T u[3], const T E[3], const T B[3], T eps)
     u[0] = sf * (px + pt * ax + (py * az - pz * ay));
     u[1] = sf * (py + pt * ay + (pz * ax - px * az));
     u[2] = sf * (pz + pt * az + (px * ay - py * ax));
+    return ign;
 }
 
 template <typename T>

@@ -190,7 +190,7 @@ __global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     unsigned long long acc = 0;
     for (int r = 0; r < n_runs; ++r) {
-        unsigned long long *c = runs[r].ctr;
+        const gptr<unsigned long long> c = glb(runs[r].ctr);
         c[kPartSteps] += c[kTotal] - c[kDeadSinceSort];
         const int K = runs[r].sort_interval;
         const bool now = K > 0 && (c[kNeedSort] != 0 || c[kStep] % (unsigned long long)K == 0);
@@ -212,7 +212,7 @@ __global__ void k_sort_finish(const RunDev<T> *__restrict__ runs, int n_runs, in
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     unsigned long long acc = 0;
     for (int r = 0; r < n_runs; ++r) {
-        unsigned long long *c = runs[r].ctr;
+        const gptr<unsigned long long> c = glb(runs[r].ctr);
         if (c[kSortNow]) {
             c[kDeleted] += c[kDeadSinceSort];
             c[kDeadSinceSort] = 0;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ ru
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
     const size_t n = R.L.size();
-    T *f0 = R.fld[cFR], *f1 = R.fld[cFTH], *f2 = R.fld[cFPH];
+    const gptr<T> f0 = glb(R.fld[cFR]), f1 = glb(R.fld[cFTH]), f2 = glb(R.fld[cFPH]);
     const size_t b = (size_t)(blockIdx.x - off[r]) * (256 * kZeroPerThread) + threadIdx.x;
 #pragma unroll
     for (int q = 0; q < kZeroPerThread; ++q) {
@@ -250,6 +250,35 @@ __global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ ru
             f0[e] = (T)0;
             f1[e] = (T)0;
             f2[e] = (T)0;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr<const T> __restrict__ Eth,
+                                             gptr<const T> __restrict__ Eph, gptr<T> __restrict__ Br,
+                                             gptr<T> __restrict__ Bth, gptr<T> __restrict__ Bph, const Metric<T> &m,
+                                             const Layout &L, int i0, int j, T hc)
+{
+    const int nr = L.nr, nth = L.nth;
+    const gptr<const T> s = glb(m.s), invr = glb(m.invr), icBr = glb(m.icBr), rn = glb(m.r_node),
+                        idr2 = glb(m.idr2), dr = glb(m.dr), idth = glb(m.idth);
+#pragma unroll
+    for (int rs = 0; rs < kRowSteps; ++rs) {
+        const int i = i0 + rs;
+        if (i > nr) break;
+        if (i >= 1 && i < nr && j < nth) {
+            const T circ = Eph[L.at(i, j)] * s[j] - Eph[L.at(i, j + 1)] * s[j + 1];
+            Br[L.at(i, j)] += hc * circ * invr[i] * icBr[j];
+        }
+        if (i < nr && j >= 1 && j < nth) {
+            const T circ = Eph[L.at(i + 1, j)] * rn[i + 1 + L.G] - Eph[L.at(i, j)] * rn[i + L.G];
+            Bth[L.at(i, j)] += hc * circ * idr2[i];
+        }
+        if (i < nr && j < nth) {
+            const T a = Eth[L.at(i, j)] * rn[i + L.G] - Eth[L.at(i + 1, j)] * rn[i + 1 + L.G];
+            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * dr[i] * idth[j];
+            Bph[L.at(i, j)] += hc * (a - b) * idr2[i];
         }
     }
 }
@@ -263,74 +292,60 @@ __global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ r
 {
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    const Layout L = R.L;
+    const Cell2 q = block_cell(blockIdx.x - off[r], R.L.nth + 1);
+    if (q.j > R.L.nth) return;
+    faraday_rows<T>(glb((const T *)R.fld[cER]), glb((const T *)R.fld[cETH]), glb((const T *)R.fld[cEPH]),
+                    glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j, hc_frac * R.c);
+}
+
+// E += (c circulation(B) - F) / area, then the lossy-layer factor on E.
+template <typename T>
+__device__ __forceinline__ void ampere_rows(gptr<const T> __restrict__ Br, gptr<const T> __restrict__ Bth,
+                                            gptr<const T> __restrict__ Bph, gptr<const T> __restrict__ Fr,
+                                            gptr<const T> __restrict__ Fth, gptr<const T> __restrict__ Fph,
+                                            gptr<T> __restrict__ Er, gptr<T> __restrict__ Eth,
+                                            gptr<T> __restrict__ Eph, const Metric<T> &m, const Layout &L, int i0,
+                                            int j, T c)
+{
     const int nr = L.nr, nth = L.nth;
-    const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
-    const int j = q.j;
-    if (j > nth) return;
-    const Metric<T> m = R.m;
-    const T hc = hc_frac * R.c;
-    const T *__restrict__ Er = R.fld[cER], *__restrict__ Eth = R.fld[cETH], *__restrict__ Eph = R.fld[cEPH];
-    T *__restrict__ Br = R.fld[cBR], *__restrict__ Bth = R.fld[cBTH], *__restrict__ Bph = R.fld[cBPH];
+    const gptr<const T> sb = glb(m.sb), invrb = glb(m.invrb), invA = glb(m.invA), idkb = glb(m.idkb),
+                        ab_half = glb(m.ab_half), rb = glb(m.rb), isb2pi = glb(m.isb2pi), idrb2 = glb(m.idrb2),
+                        ab_int = glb(m.ab_int), drb = glb(m.drb), idthb = glb(m.idthb);
 #pragma unroll
     for (int rs = 0; rs < kRowSteps; ++rs) {
-        const int i = q.i + rs;
+        const int i = i0 + rs;
         if (i > nr) break;
+        if (i < nr) {
+            const T t1 = j < nth ? sb[j] * Bph[L.at(i, j)] : (T)0;
+            const T t0 = j > 0 ? sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
+            const size_t e = L.at(i, j);
+            Er[e] = (Er[e] + (c * (t1 - t0) * invrb[i] - Fr[e] * invA[i]) * idkb[j]) * ab_half[i];
+        }
         if (i >= 1 && i < nr && j < nth) {
-            const T circ = Eph[L.at(i, j)] * m.s[j] - Eph[L.at(i, j + 1)] * m.s[j + 1];
-            Br[L.at(i, j)] += hc * circ * m.invr[i] * m.icBr[j];
+            const T circ = rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - rb[i + L.G] * Bph[L.at(i, j)];
+            const size_t e = L.at(i, j);
+            Eth[e] = (Eth[e] + (c * circ - Fth[e] * isb2pi[j]) * idrb2[i]) * ab_int[i];
         }
-        if (i < nr && j >= 1 && j < nth) {
-            const T circ = Eph[L.at(i + 1, j)] * m.r_node[i + 1 + L.G] - Eph[L.at(i, j)] * m.r_node[i + L.G];
-            Bth[L.at(i, j)] += hc * circ * m.idr2[i];
-        }
-        if (i < nr && j < nth) {
-            const T a = Eth[L.at(i, j)] * m.r_node[i + L.G] - Eth[L.at(i + 1, j)] * m.r_node[i + 1 + L.G];
-            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * m.dr[i] * m.idth[j];
-            Bph[L.at(i, j)] += hc * (a - b) * m.idr2[i];
+        if (i >= 1 && i < nr && j >= 1 && j < nth) {
+            const T a = rb[i + L.G] * Bth[L.at(i, j)] - rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
+            const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * drb[i] * idthb[j];
+            const size_t e = L.at(i, j);
+            Eph[e] = (Eph[e] + (c * (a - b) - Fph[e] * idthb[j]) * idrb2[i]) * ab_int[i];
         }
     }
 }
 
-// E += (c circulation(B) - F) / area, then the lossy-layer factor on E.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ampere(const RunDev<T> *__restrict__ runs, int n_runs,
                                                 const int *__restrict__ off)
 {
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    const Layout L = R.L;
-    const int nr = L.nr, nth = L.nth;
-    const Cell2 q = block_cell(blockIdx.x - off[r], nth + 1);
-    const int j = q.j;
-    if (j > nth) return;
-    const Metric<T> m = R.m;
-    const T c = R.c;
-    const T *__restrict__ Br = R.fld[cBR], *__restrict__ Bth = R.fld[cBTH], *__restrict__ Bph = R.fld[cBPH];
-    const T *__restrict__ Fr = R.ffin[0], *__restrict__ Fth = R.ffin[1], *__restrict__ Fph = R.ffin[2];
-    T *__restrict__ Er = R.fld[cER], *__restrict__ Eth = R.fld[cETH], *__restrict__ Eph = R.fld[cEPH];
-#pragma unroll
-    for (int rs = 0; rs < kRowSteps; ++rs) {
-        const int i = q.i + rs;
-        if (i > nr) break;
-        if (i < nr) {
-            const T t1 = j < nth ? m.sb[j] * Bph[L.at(i, j)] : (T)0;
-            const T t0 = j > 0 ? m.sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
-            T &e = Er[L.at(i, j)];
-            e = (e + (c * (t1 - t0) * m.invrb[i] - Fr[L.at(i, j)] * m.invA[i]) * m.idkb[j]) * m.ab_half[i];
-        }
-        if (i >= 1 && i < nr && j < nth) {
-            const T circ = m.rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - m.rb[i + L.G] * Bph[L.at(i, j)];
-            T &e = Eth[L.at(i, j)];
-            e = (e + (c * circ - Fth[L.at(i, j)] * m.isb2pi[j]) * m.idrb2[i]) * m.ab_int[i];
-        }
-        if (i >= 1 && i < nr && j >= 1 && j < nth) {
-            const T a = m.rb[i + L.G] * Bth[L.at(i, j)] - m.rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
-            const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * m.drb[i] * m.idthb[j];
-            T &e = Eph[L.at(i, j)];
-            e = (e + (c * (a - b) - Fph[L.at(i, j)] * m.idthb[j]) * m.idrb2[i]) * m.ab_int[i];
-        }
-    }
+    const Cell2 q = block_cell(blockIdx.x - off[r], R.L.nth + 1);
+    if (q.j > R.L.nth) return;
+    ampere_rows<T>(glb((const T *)R.fld[cBR]), glb((const T *)R.fld[cBTH]), glb((const T *)R.fld[cBPH]),
+                   glb(R.ffin[0]), glb(R.ffin[1]), glb(R.ffin[2]), glb(R.fld[cER]), glb(R.fld[cETH]),
+                   glb(R.fld[cEPH]), R.m, R.L, q.i, q.j, R.c);
 }
 
 // Lossy layer on B over rows nr - absorb_cells - 1 .. nr (the factor is 1
@@ -345,16 +360,16 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
     const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
     const int j = q.j;
     if (j > L.nth) return;
-    const Metric<T> m = R.m;
-    T *Br = R.fld[cBR], *Bth = R.fld[cBTH], *Bph = R.fld[cBPH];
+    const gptr<const T> ab_int = glb(R.m.ab_int), ab_half = glb(R.m.ab_half);
+    const gptr<T> Br = glb(R.fld[cBR]), Bth = glb(R.fld[cBTH]), Bph = glb(R.fld[cBPH]);
     for (int rs = 0; rs < kRowSteps; ++rs) {
         const int i = L.nr - R.absorb_cells - 1 + q.i + rs;
         if (i > L.nr) return;
         if (i < 0) continue;
-        if (j < L.nth) Br[L.at(i, j)] *= m.ab_int[i];
+        if (j < L.nth) Br[L.at(i, j)] *= ab_int[i];
         if (i < L.nr) {
-            Bth[L.at(i, j)] *= m.ab_half[i];
-            if (j < L.nth) Bph[L.at(i, j)] *= m.ab_half[i];
+            Bth[L.at(i, j)] *= ab_half[i];
+            if (j < L.nth) Bph[L.at(i, j)] *= ab_half[i];
         }
     }
 }
@@ -365,12 +380,12 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
 // back onto its mirror image, with a plus sign for integer-j components and
 // a minus sign for the theta component; radially the array is extended by
 // zeros beyond rows [-G, last row].
-template <typename T>
-__device__ inline T theta_pass(const T *__restrict__ a, const Layout &L, int i, int j, int kind)
+template <typename T, typename Ptr>
+__device__ inline T theta_pass(Ptr a, const Layout &L, int i, int j, int kind)
 {
     const int nth = L.nth;
     const int ncol = kind ? nth : nth + 1;
-    const T *row = a + L.at(i, 0);
+    const Ptr row = a + L.at(i, 0);
     T v = (T)0.5 * row[j];
     if (j > 0) v += (T)0.25 * row[j - 1];
     if (j + 1 < ncol) v += (T)0.25 * row[j + 1];
@@ -403,8 +418,8 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const int ncol = kind ? L.nth : L.nth + 1;
     const int last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
     if (j >= ncol) return;
-    const T *__restrict__ a = (pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp];
-    T *__restrict__ dst = (pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp];
+    const gptr<const T> a = glb((const T *)((pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp]));
+    const gptr<T> dst = glb((pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp]);
     const int i0 = -L.G + q.i;
     if (i0 > last) return;
     // theta passes of rows i0 - 1 .. i0 + kRowSteps, zero outside [-G, last]
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
 #pragma unroll
     for (int rs = 0; rs < kRowSteps + 2; ++rs) {
         const int i = i0 - 1 + rs;
-        tp[rs] = (i >= -L.G && i <= last) ? theta_pass(a, L, i, j, kind) : (T)0;
+        tp[rs] = (i >= -L.G && i <= last) ? theta_pass<T>(a, L, i, j, kind) : (T)0;
     }
 #pragma unroll
     for (int rs = 0; rs < kRowSteps; ++rs) {
@@ -433,9 +448,9 @@ __global__ __launch_bounds__(256) void k_filter_nodes(const T *__restrict__ src,
     const int i = -L.G + (int)(blockIdx.y * blockDim.y + threadIdx.y);
     const int last = L.nr + L.G;
     if (i > last || j > L.nth) return;
-    T v = (T)0.5 * theta_pass(src, L, i, j, 0);
-    if (i > -L.G) v += (T)0.25 * theta_pass(src, L, i - 1, j, 0);
-    if (i < last) v += (T)0.25 * theta_pass(src, L, i + 1, j, 0);
+    T v = (T)0.5 * theta_pass<T>(src, L, i, j, 0);
+    if (i > -L.G) v += (T)0.25 * theta_pass<T>(src, L, i - 1, j, 0);
+    if (i < last) v += (T)0.25 * theta_pass<T>(src, L, i + 1, j, 0);
     dst[L.at(i, j)] = v;
 }
 
@@ -447,17 +462,17 @@ __global__ __launch_bounds__(256) void k_filter_nodes(const T *__restrict__ src,
 template <typename T>
 struct PushArgs {
     Layout L;
-    Fields<T> f;          // E, B (read) and F (deposit target)
+    GFields<T> f;         // E, B (read) and F (deposit target)
     Background bg;
     int r_kind, th_kind, mover, n_filt;
     T c, dxi, inv_dxi, nth_f, two_over_nth, pi_over_nth, inv_pi_over_nth, eps0, inv_rl;
-    const T *r_node;      // r(i) at [i + G]
-    const T *k_node;      // cos theta_j
-    uint32_t *cell;
-    T *dx, *dy, *ur, *ut, *up;
-    const T *w;
-    unsigned long long *n_dead;
-    int *status;
+    gptr<const T> r_node; // r(i) at [i + G]
+    gptr<const T> k_node; // cos theta_j
+    gptr<uint32_t> cell;
+    gptr<T> dx, dy, ur, ut, up;
+    gptr<const T> w;
+    gptr<unsigned long long> n_dead;
+    gptr<int> status;
 };
 
 template <typename T>
@@ -466,7 +481,7 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     PushArgs<T> p;
     p.L = R.L;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) p.f.c[q] = R.fld[q];
+    for (int q = 0; q < 9; ++q) p.f.c[q] = glb(R.fld[q]);
     p.bg = R.bg;
     p.r_kind = R.r_kind;
     p.th_kind = R.th_kind;
@@ -481,23 +496,23 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     p.inv_pi_over_nth = R.inv_pi_over_nth;
     p.eps0 = R.eps0;
     p.inv_rl = (T)inv_light_cylinder(R.omega, R.t_spin, R.cd, step);
-    p.r_node = R.m.r_node;
-    p.k_node = R.m.k;
-    p.cell = R.cell[cur];
-    p.dx = R.arr[cur][0];
-    p.dy = R.arr[cur][1];
-    p.ur = R.arr[cur][2];
-    p.ut = R.arr[cur][3];
-    p.up = R.arr[cur][4];
-    p.w = R.arr[cur][5];
-    p.n_dead = R.ctr + kDeadSinceSort;
-    p.status = R.status;
+    p.r_node = glb(R.m.r_node);
+    p.k_node = glb(R.m.k);
+    p.cell = glb(R.cell[cur]);
+    p.dx = glb(R.arr[cur][0]);
+    p.dy = glb(R.arr[cur][1]);
+    p.ur = glb(R.arr[cur][2]);
+    p.ut = glb(R.arr[cur][3]);
+    p.up = glb(R.arr[cur][4]);
+    p.w = glb((const T *)R.arr[cur][5]);
+    p.n_dead = glb(R.ctr + kDeadSinceSort);
+    p.status = glb(R.status);
     return p;
 }
 
 template <typename T>
 struct GlobalView {
-    const Fields<T> *f;
+    const GFields<T> *f;
     Layout L;
     __device__ T get(int c, int i, int j) const { return f->c[c][L.at(i, j)]; }
     // half-integer-j component continued across the axis with parity sgn
@@ -511,16 +526,30 @@ struct GlobalView {
 
 template <typename T>
 struct GlobalDep {
-    T *F[3];
+    gptr<T> F[3];
     Layout L;
-    __device__ void add(int c, int i, int j, T v) const { unsafeAtomicAdd(&F[c][L.at(i, j)], v); }
+    __device__ void add(int c, int i, int j, T v) const { atomic_add(F[c] + L.at(i, j), v); }
 };
+
+// Entries per LDS plane of a push work-group: a compile-time stride, so
+// that every plane of one (i, j) is reached with an immediate offset from
+// one address.  FP32: nine planes (6 x 4 B fields, 3 x 8 B deposits) plus
+// the work-group's few static bytes within 40 KB, so that four work-groups
+// share a CU's 160 KB; FP64 (two work-groups per CU, as its registers
+// allow): within 80 KB.
+template <typename T>
+constexpr int lds_plane();
+template <>
+constexpr int lds_plane<float>() { return 840; }
+template <>
+constexpr int lds_plane<double>() { return 1120; }
 
 template <typename T>
 struct LdsView {
+    static constexpr int P = lds_plane<T>();
     const T *s;
-    int cap, i0, j0, C;
-    __device__ T get(int c, int i, int j) const { return s[c * cap + (i - i0) * C + (j - j0)]; }
+    int i0, j0, C;
+    __device__ T get(int c, int i, int j) const { return s[c * P + (i - i0) * C + (j - j0)]; }
     __device__ T geth(int c, int i, int j, T) const { return get(c, i, j); } // mirror staged
 };
 
@@ -554,12 +583,13 @@ constexpr int fixed_bits<double>() { return 48; }
 
 template <typename T>
 struct LdsDep {
+    static constexpr int P = lds_plane<T>();
     long long *s;
-    int cap, i0, j0, C;
+    int i0, j0, C;
     T scale;
     __device__ void add(int c, int i, int j, T v) const
     {
-        atomicAdd((unsigned long long *)&s[c * cap + (i - i0) * C + (j - j0)], (unsigned long long)to_fixed(v, scale));
+        atomicAdd((unsigned long long *)&s[c * P + (i - i0) * C + (j - j0)], (unsigned long long)to_fixed(v, scale));
     }
 };
 
@@ -605,11 +635,24 @@ __device__ inline void vb_piece(const D &d, int i, int j, T xa, T ya, T xb, T yb
     d.add(1, i + 1, j, qy * mx);
 }
 
+// One straight piece of a move, in the frame of cell (i, j): deposited in
+// the cell that holds its midpoint (the last row of cells takes y = nth).
+template <typename T, typename D>
+__device__ __forceinline__ void vb_segment(const D &d, int i, int j, int nth, T xa, T ya, T xb, T yb, T Q)
+{
+    const T mx = (T)0.5 * (xa + xb), my = (T)0.5 * (ya + yb);
+    const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
+    int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
+    if (j + dj > nth - 1) dj = nth - 1 - j;
+    vb_piece(d, i + di, j + dj, xa - (T)di, ya - (T)dj, xb - (T)di, yb - (T)dj, Q);
+}
+
 // Villasenor-Buneman deposit of the move (x0, y0) -> (x1, y1), both in the
 // frame of cell (i, j) (start in [0,1)^2, end within one cell of it): cut at
-// the cell faces it crosses, each piece deposited in its own cell; plus the
-// ring charge Q dphi / 2 pi crossing a meridional half-plane, assigned
-// bilinearly at the midpoint of the move.
+// the cell faces it crosses (at most two), in the order met along the
+// path, each piece deposited in its own cell; plus the ring charge
+// Q dphi / 2 pi crossing a meridional half-plane, assigned bilinearly at the
+// midpoint of the move.
 template <typename T, typename D>
 __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0, T x1, T y1, T Q, T dphi)
 {
@@ -617,35 +660,29 @@ __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0,
     T X = 0, Y = 0;
     if (x1 >= (T)1) { cx = 1; X = (T)1; } else if (x1 < (T)0) { cx = -1; X = (T)0; }
     if (y1 >= (T)1 && j < nth - 1) { cy = 1; Y = (T)1; } else if (y1 < (T)0) { cy = -1; Y = (T)0; }
-    T px[4], py[4];
-    int np = 0;
-    px[np] = x0; py[np] = y0; ++np;
+    // split points s1, s2 (n of them) between the start and the end
+    int n = 0;
+    T s1x = x1, s1y = y1, s2x = x1, s2y = y1;
     if (cx && cy) {
         const T tx = FM<T>::div(X - x0, x1 - x0), ty = FM<T>::div(Y - y0, y1 - y0);
+        const T yx = y0 + tx * (y1 - y0), xy = x0 + ty * (x1 - x0);
         if (tx < ty) {
-            px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
-            px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
+            s1x = X; s1y = yx; s2x = xy; s2y = Y; n = 2;
         } else if (ty < tx) {
-            px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
-            px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
+            s1x = xy; s1y = Y; s2x = X; s2y = yx; n = 2;
         } else {
-            px[np] = X; py[np] = Y; ++np;
+            s1x = X; s1y = Y; n = 1;
         }
     } else if (cx) {
         const T tx = FM<T>::div(X - x0, x1 - x0);
-        px[np] = X; py[np] = y0 + tx * (y1 - y0); ++np;
+        s1x = X; s1y = y0 + tx * (y1 - y0); n = 1;
     } else if (cy) {
         const T ty = FM<T>::div(Y - y0, y1 - y0);
-        px[np] = x0 + ty * (x1 - x0); py[np] = Y; ++np;
+        s1x = x0 + ty * (x1 - x0); s1y = Y; n = 1;
     }
-    px[np] = x1; py[np] = y1; ++np;
-    for (int q = 0; q + 1 < np; ++q) {
-        const T mx = (T)0.5 * (px[q] + px[q + 1]), my = (T)0.5 * (py[q] + py[q + 1]);
-        const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
-        int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
-        if (j + dj > nth - 1) dj = nth - 1 - j;
-        vb_piece(d, i + di, j + dj, px[q] - (T)di, py[q] - (T)dj, px[q + 1] - (T)di, py[q + 1] - (T)dj, Q);
-    }
+    vb_segment(d, i, j, nth, x0, y0, s1x, s1y, Q);
+    if (n >= 1) vb_segment(d, i, j, nth, s1x, s1y, s2x, s2y, Q);
+    if (n >= 2) vb_segment(d, i, j, nth, s2x, s2y, x1, y1, Q);
     const T mx = (T)0.5 * (x0 + x1), my = (T)0.5 * (y0 + y1);
     const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
     int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
@@ -677,6 +714,7 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     T r = p.r_node[i + p.L.G];
     if (p.r_kind == 0) r *= FM<T>::exp(fx * p.dxi);
     else r += fx * p.dxi;
+    const T ir = FM<T>::rcp(r);
     T k, s;
     if (p.th_kind == 0) {
         // sin theta = (2/nth) sqrt(y (nth - y)); both factors formed from the
@@ -699,26 +737,34 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     const bool outer = i > nr || (i == nr && fx > (T)0); // beyond the outer conductor: ballistic
     const bool inner = i < 0;                            // inside the star: corotation field only
     const T eps = w > (T)0 ? p.eps0 : (w < (T)0 ? -p.eps0 : (T)0);
+    T ig; // 1 / gamma of the new momentum
     if (!outer && eps != (T)0) {
         T E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
         if (!inner) gather(view, i, j, fx, fy, E, B);
-        add_background(p.bg, p.inv_rl, inner, r, k, s, E, B);
+        add_background(p.bg, p.inv_rl, inner, r, ir, k, s, E, B);
         const T Ec[3] = {s * E[0] + k * E[1], E[2], k * E[0] - s * E[1]};
         const T Bc[3] = {s * B[0] + k * B[1], B[2], k * B[0] - s * B[1]};
-        if (p.mover == 0) vay_push(uc, Ec, Bc, eps);
-        else boris_push(uc, Ec, Bc, eps);
+        if (p.mover == 0) {
+            ig = vay_push(uc, Ec, Bc, eps);
+        } else {
+            boris_push(uc, Ec, Bc, eps);
+            ig = FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+        }
+    } else {
+        ig = FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
     }
     // displacement over the step, relative to r
-    const T vg = p.c * FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
-    const T ir = FM<T>::rcp(r);
+    const T vg = p.c * ig;
     const T ex = uc[0] * vg * ir, ey = uc[1] * vg * ir, ez = uc[2] * vg * ir;
     const T xs = s + ex, zs = k + ez;                    // (R', Z') / r
     const T q = (T)2 * (s * ex + k * ez) + ex * ex + ey * ey + ez * ez;
-    const T sq = FM<T>::sqrt((T)1 + q);                  // r' / r
+    T sq, isq;                                           // r' / r and its inverse
+    FM<T>::sqrt_rsqrt((T)1 + q, sq, isq);
     const T eta = FM<T>::div(q, (T)1 + sq);              // r' / r - 1
     const T dX = p.r_kind == 0 ? FM<T>::log1p(eta) * p.inv_dxi : r * eta * p.inv_dxi;
-    const T Rn = FM<T>::sqrt(xs * xs + ey * ey);
-    const T isq = FM<T>::rcp(sq);
+    const T Rn2 = xs * xs + ey * ey;
+    T Rn = (T)0, iR = (T)0;                              // R' / r and its inverse
+    if (Rn2 > (T)0) FM<T>::sqrt_rsqrt(Rn2, Rn, iR);
     T dY;
     if (p.th_kind == 0) dY = (T)-0.5 * p.nth_f * ((ez - k * eta) * isq);
     else dY = FM<T>::atan2(Rn * k - zs * s, Rn * s + zs * k) * p.inv_pi_over_nth;
@@ -727,12 +773,11 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     if (Y1 < (T)(-j)) Y1 = (T)(-j);                      // reflection at the poles: y' in [0, nth]
     if (Y1 > (T)(nth - j)) Y1 = (T)(nth - j);
     if (!(fabs(X1 - fx) < (T)1 && fabs(Y1 - fy) < (T)1)) { // CFL (or a non-finite value)
-        atomicOr(p.status, 1);
+        atomic_or(p.status, 1);
         return;
     }
     T cph = (T)1, sph = (T)0;
     if (Rn > (T)0) {
-        const T iR = FM<T>::rcp(Rn);
         cph = xs * iR;
         sph = ey * iR;
     }
@@ -754,7 +799,7 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     const int lim = p.n_filt + 1;                        // whole filtered shape inside a conductor
     if (ni < -lim || ni > nr + lim || (ni == nr + lim && nx > (T)0)) {
         p.cell[idx] = kDead;
-        atomicAdd(p.n_dead, 1ull);
+        atomic_add(p.n_dead, 1ull);
     } else {
         p.cell[idx] = pack_cell(ni, nj);
     }
@@ -772,17 +817,19 @@ __device__ inline int wave_max(int v)
 }
 
 // LDS of a push work-group: six field planes of T, then three 64-bit
-// fixed-point deposit planes (8-byte aligned).
+// fixed-point deposit planes (8-byte aligned), lds_plane<T>() entries each.
 template <typename T>
-__host__ __device__ constexpr size_t lds_field_bytes(int cap)
+__host__ __device__ constexpr size_t lds_field_bytes()
 {
-    return ((size_t)6 * cap * sizeof(T) + 7) / 8 * 8;
+    return ((size_t)6 * lds_plane<T>() * sizeof(T) + 7) / 8 * 8;
 }
 template <typename T>
-__host__ __device__ constexpr size_t lds_push_bytes(int cap)
+__host__ __device__ constexpr size_t lds_push_bytes()
 {
-    return lds_field_bytes<T>(cap) + (size_t)3 * cap * sizeof(long long);
+    return lds_field_bytes<T>() + (size_t)3 * lds_plane<T>() * sizeof(long long);
 }
+static_assert(lds_push_bytes<float>() + 512 <= 40 * 1024, "FP32 push LDS: four work-groups per CU");
+static_assert(lds_push_bytes<double>() + 512 <= 80 * 1024, "FP64 push LDS: two work-groups per CU");
 
 // Slot of iteration q of thread t inside a chunk: each pass of the 256
 // threads reads 256 consecutive particles (full cache lines in and out).
@@ -804,8 +851,17 @@ __device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
 // range b % 8 from that range's atomic counter until the range is
 // exhausted, so late-starting work-groups never leave a tail of unbalanced
 // work.
+// Waves per SIMD the push is compiled for: FP32 four (128 registers), FP64
+// two (LDS and registers allow no more).
+template <typename T>
+constexpr int push_waves();
+template <>
+constexpr int push_waves<float>() { return 4; }
+template <>
+constexpr int push_waves<double>() { return 2; }
+
 template <typename T, int PPT>
-__global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs, int n_runs,
+__global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *__restrict__ runs, int n_runs,
                                               const unsigned long long *__restrict__ chunk_off,
                                               unsigned int *__restrict__ work)
 {
@@ -818,21 +874,22 @@ __global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs
     const unsigned long long lo = nch * xcd / 8, hi = nch * (xcd + 1) / 8;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (;;) {
-        if (tid == 0) s_next = atomicAdd(&work[xcd], 1u);
+        if (tid == 0) s_next = atomic_add_fetch_old(glb(work + xcd), 1u);
         __syncthreads();
         const unsigned long long gch = lo + (unsigned long long)__builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (gch >= hi) break;
         const int r = __builtin_amdgcn_readfirstlane(run_of(chunk_off, n_runs, gch));
         const RunDev<T> &R = runs[r];
-        const unsigned long long *ctr = R.ctr;
+        const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
         const unsigned long long n = ctr[kTotal];
         const int cur = (int)ctr[kCur];
         const PushArgs<T> p = push_args(R, cur, (double)ctr[kStep]);
         const int cap = R.lds_cap;
         const int nth = p.L.nth;
-        T *sm = reinterpret_cast<T *>(smem_raw);                                 // 6 field planes
-        long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>(cap)); // 3 deposit planes
+        constexpr int P = lds_plane<T>();
+        T *sm = reinterpret_cast<T *>(smem_raw);                                  // 6 field planes
+        long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>()); // 3 deposit planes
         const size_t base = (size_t)(gch - chunk_off[r]) * CH;
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
@@ -880,22 +937,22 @@ __global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs
                 if (gj < 0) { hj = -1 - gj; so = (T)-1; }
                 else if (gj >= nth) { hj = 2 * nth - 1 - gj; so = (T)-1; }
                 const bool vh = hj >= 0 && hj < nth;
-                sm[cER * cap + e] = vi ? p.f.c[cER][p.L.at(gi, gj)] : (T)0;
-                sm[cEPH * cap + e] = vi ? p.f.c[cEPH][p.L.at(gi, gj)] : (T)0;
-                sm[cBTH * cap + e] = vi ? p.f.c[cBTH][p.L.at(gi, gj)] : (T)0;
-                sm[cETH * cap + e] = vh ? so * p.f.c[cETH][p.L.at(gi, hj)] : (T)0;
-                sm[cBR * cap + e] = vh ? p.f.c[cBR][p.L.at(gi, hj)] : (T)0;
-                sm[cBPH * cap + e] = vh ? so * p.f.c[cBPH][p.L.at(gi, hj)] : (T)0;
+                sm[cER * P + e] = vi ? p.f.c[cER][p.L.at(gi, gj)] : (T)0;
+                sm[cEPH * P + e] = vi ? p.f.c[cEPH][p.L.at(gi, gj)] : (T)0;
+                sm[cBTH * P + e] = vi ? p.f.c[cBTH][p.L.at(gi, gj)] : (T)0;
+                sm[cETH * P + e] = vh ? so * p.f.c[cETH][p.L.at(gi, hj)] : (T)0;
+                sm[cBR * P + e] = vh ? p.f.c[cBR][p.L.at(gi, hj)] : (T)0;
+                sm[cBPH * P + e] = vh ? so * p.f.c[cBPH][p.L.at(gi, hj)] : (T)0;
                 sd[e] = 0;
-                sd[cap + e] = 0;
-                sd[2 * cap + e] = 0;
+                sd[P + e] = 0;
+                sd[2 * P + e] = 0;
                 rr += dr;
                 cc += dc;
                 if (cc >= C) { cc -= C; ++rr; }
             }
             __syncthreads();
-            const LdsView<T> view{sm, cap, i0, j0, C};
-            const LdsDep<T> dep{sd, cap, i0, j0, C, R.dep_scale};
+            const LdsView<T> view{sm, i0, j0, C};
+            const LdsDep<T> dep{sd, i0, j0, C, R.dep_scale};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const size_t idx = chunk_slot(base, tid, q);
@@ -910,8 +967,8 @@ __global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs
                     const size_t g = p.L.at(i0 + fr, j0 + fc);
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) {
-                        const long long v = sd[comp * cap + e];
-                        if (v != 0) unsafeAtomicAdd(&p.f.c[cFR + comp][g], (T)v * inv);
+                        const long long v = sd[comp * P + e];
+                        if (v != 0) atomic_add(p.f.c[cFR + comp] + g, (T)v * inv);
                     }
                     fr += dr;
                     fc += dc;
@@ -920,7 +977,7 @@ __global__ __launch_bounds__(256) void k_push(const RunDev<T> *__restrict__ runs
             }
             __syncthreads();
         } else {
-            if (tid == 0 && cap > 0) atomicAdd(R.ctr + kGlobalChunks, 1ull);
+            if (tid == 0 && cap > 0) atomic_add(glb(R.ctr + kGlobalChunks), 1ull);
             const GlobalView<T> view{&p.f, p.L};
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1
@@ -946,7 +1003,7 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
     __shared__ long long scan[1024];
     __shared__ int ok;
     const RunDev<T> &R = runs[blockIdx.x];
-    unsigned long long *ctr = R.ctr;
+    const gptr<unsigned long long> ctr = glb(R.ctr);
     const int tid = threadIdx.x;
     const uint64_t step = ctr[kStep];
     if (!R.inject) {
@@ -963,11 +1020,11 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
     long long mine = 0;
     for (int jj = j0; jj < j1; ++jj) {
         double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-        add_background(R.bg, irl, false, R.rb0, R.kn[jj], R.sn[jj], E, B);
-        const double sigma = (double)R.fld[cER][L.at(0, jj)] + E[0];
-        const double cnew = R.carry[jj] + R.f_inj * fabs(sigma) * R.Aj[jj] / R.q_inj;
+        add_background(R.bg, irl, false, R.rb0, glb(R.kn)[jj], glb(R.sn)[jj], E, B);
+        const double sigma = (double)glb(R.fld[cER])[L.at(0, jj)] + E[0];
+        const double cnew = glb(R.carry)[jj] + R.f_inj * fabs(sigma) * glb(R.Aj)[jj] / R.q_inj;
         const double fl = floor(cnew);
-        R.carry[jj] = cnew - fl;
+        glb(R.carry)[jj] = cnew - fl;
         m[jj - j0] = (long long)fl;
         mine += (long long)fl;
     }
@@ -986,14 +1043,15 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
     __syncthreads();
     if (!ok) {
         if (tid == 0) {
-            atomicOr(R.status, 2);
+            atomic_or(glb(R.status), 2);
             ctr[kStep] = step + 1;
         }
         return;
     }
-    uint32_t *cell = R.cell[cur];
-    T *const *a = R.arr[cur];
-    uint64_t *id = R.id[cur];
+    const gptr<uint32_t> cell = glb(R.cell[cur]);
+    const gptr<T> a[6] = {glb(R.arr[cur][0]), glb(R.arr[cur][1]), glb(R.arr[cur][2]),
+                          glb(R.arr[cur][3]), glb(R.arr[cur][4]), glb(R.arr[cur][5])};
+    const gptr<uint64_t> id = R.id[cur] ? glb(R.id[cur]) : nullptr;
     for (int jj = j0; jj < j1; ++jj) {
         const double ylo = jj - 0.5 < 0.0 ? 0.0 : jj - 0.5;
         const double yhi = jj + 0.5 > nth ? (double)nth : jj + 0.5;
@@ -1051,11 +1109,11 @@ __global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__
 {
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    if (!R.ctr[kSortNow]) return;
+    if (!glb(R.ctr)[kSortNow]) return;
     const int e = (blockIdx.x - off[r]) * 256 + threadIdx.x;
     if (e <= R.tm.n_keys) {
-        R.counts[e] = 0;
-        R.cursor[e] = 0;
+        glb(R.counts)[e] = 0;
+        glb(R.cursor)[e] = 0;
     }
 }
 
@@ -1074,10 +1132,11 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
     for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
         const RunDev<T> &R = runs[r];
-        const unsigned long long n = R.ctr[kTotal];
-        const uint32_t *cell = R.cell[R.ctr[kCur]];
+        const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
+        const unsigned long long n = ctr[kTotal];
+        const gptr<const uint32_t> cell = glb((const uint32_t *)R.cell[ctr[kCur]]);
         const TileMap tm = R.tm;
-        unsigned int *counts = R.counts;
+        const gptr<unsigned int> counts = glb(R.counts);
         const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
         const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
         int pend_key = -1;          // wave-uniform pending run of keys
@@ -1098,16 +1157,16 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
             const bool extend = pend_key == first_key;
             if (extend) pend_len += (unsigned int)first_len;
             if (pend_key >= 0 && (!extend || nruns > 1)) { // the pending run has ended
-                if (lane == 0 && pend_key != INT_MAX) atomicAdd(&counts[pend_key], pend_len);
+                if (lane == 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
             }
             const bool complete = head && lane != last_lane && !(lane == 0 && extend);
-            if (complete && key != INT_MAX) atomicAdd(&counts[key], (unsigned int)(next - lane));
+            if (complete && key != INT_MAX) atomic_add(counts + key, (unsigned int)(next - lane));
             if (!(extend && nruns == 1)) {
                 pend_key = last_key;
                 pend_len = (unsigned int)(64 - last_lane);
             }
         }
-        if (lane == 0 && pend_key >= 0 && pend_key != INT_MAX) atomicAdd(&counts[pend_key], pend_len);
+        if (lane == 0 && pend_key >= 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
     }
 }
 
@@ -1119,9 +1178,11 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
 {
     __shared__ unsigned long long s[1024];
     const RunDev<T> &R = runs[blockIdx.x];
-    if (!R.ctr[kSortNow]) return;
+    const gptr<unsigned long long> ctr = glb(R.ctr);
+    if (!ctr[kSortNow]) return;
     const int n_keys = R.tm.n_keys;
-    const unsigned int *counts = R.counts;
+    const gptr<const unsigned int> counts = glb((const unsigned int *)R.counts);
+    const gptr<unsigned long long> offsets = glb(R.offsets);
     const int tid = threadIdx.x;
     const int per = (n_keys + 1 + 1023) / 1024;
     const int a = tid * per, b = min(a + per, n_keys + 1);
@@ -1137,11 +1198,11 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
     }
     unsigned long long run = s[tid] - mine;
     for (int q = a; q < b; ++q) {
-        R.offsets[q] = run;
+        offsets[q] = run;
         run += counts[q];
     }
     __syncthreads();
-    if (tid == 0) R.ctr[kLive] = s[1023] - counts[n_keys];
+    if (tid == 0) ctr[kLive] = s[1023] - counts[n_keys];
 }
 
 // Stable scatter into the other buffer: each run of equal keys in a
@@ -1157,12 +1218,22 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
     for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
         const RunDev<T> &R = runs[r];
-        const unsigned long long n = R.ctr[kTotal];
-        const int cur = (int)R.ctr[kCur], nxt = cur ^ 1;
-        const uint32_t *cell = R.cell[cur];
-        uint32_t *cell_o = R.cell[nxt];
-        const uint64_t *id = R.id[cur];
-        uint64_t *id_o = R.id[nxt];
+        const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
+        const unsigned long long n = ctr[kTotal];
+        const int cur = (int)ctr[kCur], nxt = cur ^ 1;
+        const gptr<const uint32_t> cell = glb((const uint32_t *)R.cell[cur]);
+        const gptr<uint32_t> cell_o = glb(R.cell[nxt]);
+        const gptr<const uint64_t> id = R.id[cur] ? glb((const uint64_t *)R.id[cur]) : nullptr;
+        const gptr<uint64_t> id_o = glb(R.id[nxt]);
+        const gptr<const unsigned long long> offsets = glb((const unsigned long long *)R.offsets);
+        const gptr<unsigned int> cursor = glb(R.cursor);
+        gptr<const T> src[6];
+        gptr<T> dst[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            src[q] = glb((const T *)R.arr[cur][q]);
+            dst[q] = glb(R.arr[nxt][q]);
+        }
         const TileMap tm = R.tm;
         const unsigned long long cap = (unsigned long long)R.capacity;
         const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
@@ -1178,15 +1249,15 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
             const int next = after ? __ffsll((long long)after) - 1 : 64;
             const bool live = key != INT_MAX && key != tm.n_keys;
             unsigned int got = 0;
-            if (head && live) got = atomicAdd(&R.cursor[key], (unsigned int)(next - lane));
+            if (head && live) got = atomic_add_fetch_old(cursor + key, (unsigned int)(next - lane));
             const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
             got = __shfl(got, hl);
-            const unsigned long long d = live ? R.offsets[key] + got + (lane - hl) : 0;
-            if (live && d >= cap) atomicOr(R.status, 4); // never write outside the store
+            const unsigned long long d = live ? offsets[key] + got + (lane - hl) : 0;
+            if (live && d >= cap) atomic_or(glb(R.status), 4); // never write outside the store
             if (live && d < cap) {
                 cell_o[d] = c;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) R.arr[nxt][q][d] = R.arr[cur][q][idx];
+                for (int q = 0; q < 6; ++q) dst[q][d] = src[q][idx];
                 if (id) id_o[d] = id[idx];
             }
         }

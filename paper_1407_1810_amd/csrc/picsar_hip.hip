@@ -178,7 +178,7 @@ public:
         }
         for (int m = 0; m < kMaps; ++m) h[(size_t)m * (n_ + 1) + n_] = tot_[m];
         HIPCHK(hipMemcpyAsync(maps_, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
-        shm_ = max_cap > 0 ? lds_push_bytes<T>(max_cap) : 0;
+        shm_ = max_cap > 0 ? lds_push_bytes<T>() : 0;
         if (shm_ > 0) {
             const int b = (int)shm_;
             HIPCHK(hipFuncSetAttribute((const void *)k_push<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, b));
@@ -782,12 +782,9 @@ private:
         // per step in grid units) and the stencil halo (one cell below, two above)
         const int drift = sort_interval > 0 ? (7 * sort_interval + 9) / 10 : 0;
         const int Rr = 2 * tile_r + 2 * drift + 3, Cc = 2 * tile_th + 2 * drift + 3;
-        R.lds_cap = sort_interval > 0 ? std::min(Rr * Cc, kMaxLdsBytes / (6 * (int)sizeof(T) + 24)) : 0;
+        R.lds_cap = sort_interval > 0 ? std::min(Rr * Cc, lds_plane<T>()) : 0;
     }
 
-    // LDS of one push work-group: FP32 keeps four work-groups per CU (160 KB),
-    // FP64 is held at two per CU by its registers anyway
-    static constexpr int kMaxLdsBytes = sizeof(T) == 4 ? 40 * 1024 : 64 * 1024;
 
     std::vector<void *> allocs_;
     RunDev<T> rd_{};
