@@ -50,6 +50,8 @@ struct ora_sim {
     int32_t rows[NCOMP], cols[NCOMP], row0[NCOMP];
     int64_t n, cap;
     double *x, *y, *ur, *ut, *up, *w;
+    double *dp;                /* distance in y to the nearer pole, min(y, nth - y),
+                                  kept to full relative precision */
     uint64_t *id;
     double *carry;             /* fractional injection count per theta node */
     int64_t step;
@@ -108,10 +110,36 @@ static double f_th(const ora_sim *s, double y)
     return PI * y / s->p.nth;
 }
 
-static double y_of(const ora_sim *s, double cth, double sth)
+/* Near a pole the absolute coordinate y (up to nth) cannot resolve the
+ * distance to the pole that sin(theta) depends on (Sec. 3.2 writes
+ * sin(theta) through both factors y and nth - y so that neither cancels).
+ * Every particle therefore also carries dp = min(y, nth - y) to full
+ * relative precision; its trigonometric factors come from dp. */
+static double pole_dist(const ora_sim *s, double y)
 {
-    if (s->p.th_kind == ORA_TH_EQAREA) return 0.5 * s->p.nth * (1.0 - cth);
-    return s->p.nth * atan2(sth, cth) / PI;
+    return y <= 0.5 * s->p.nth ? y : s->p.nth - y;
+}
+
+static void trig_at(const ora_sim *s, double y, double dp, double *kc, double *sn)
+{
+    const int nth = s->p.nth;
+    const int south = y > 0.5 * nth;
+    if (s->p.th_kind == ORA_TH_EQAREA) {
+        const double a = dp * (nth - dp);
+        *sn = 2.0 / nth * sqrt(a > 0.0 ? a : 0.0);
+        *kc = south ? -1.0 + 2.0 * dp / nth : 1.0 - 2.0 * dp / nth;
+    } else {
+        *sn = sin(PI * dp / nth);
+        *kc = south ? -cos(PI * dp / nth) : cos(PI * dp / nth);
+    }
+}
+
+/* Distance to the nearer pole of the point (R, Z) at radius r, without
+ * cancellation: 1 - |cos(theta)| = R^2 / (r (r + |Z|)). */
+static double pole_dist_of(const ora_sim *s, double R, double Z, double r)
+{
+    if (s->p.th_kind == ORA_TH_EQAREA) return 0.5 * s->p.nth * R * R / (r * (r + fabs(Z)));
+    return s->p.nth * atan2(R, fabs(Z)) / PI;
 }
 
 /* ------------------------------------------------------------------ */
@@ -175,7 +203,7 @@ ora_sim *ora_create(const ora_params *p)
 
 static void free_particles(ora_sim *s)
 {
-    free(s->x); free(s->y); free(s->ur); free(s->ut); free(s->up); free(s->w); free(s->id);
+    free(s->x); free(s->y); free(s->ur); free(s->ut); free(s->up); free(s->w); free(s->dp); free(s->id);
     s->x = s->y = s->ur = s->ut = s->up = s->w = NULL;
     s->id = NULL;
 }
@@ -217,8 +245,8 @@ static int reserve(ora_sim *s, int64_t need)
     if (need <= s->cap) return ORA_OK;
     int64_t cap = s->cap ? s->cap : 1024;
     while (cap < need) cap *= 2;
-    double **arr[6] = {&s->x, &s->y, &s->ur, &s->ut, &s->up, &s->w};
-    for (int a = 0; a < 6; ++a) {
+    double **arr[7] = {&s->x, &s->y, &s->ur, &s->ut, &s->up, &s->w, &s->dp};
+    for (int a = 0; a < 7; ++a) {
         double *q = (double *)realloc(*arr[a], sizeof(double) * cap);
         if (!q) return ORA_ENOMEM;
         *arr[a] = q;
@@ -239,6 +267,7 @@ int ora_add_particles(ora_sim *s, int64_t n, const double *x, const double *y, c
         int64_t d = s->n + k;
         s->x[d] = x[k];
         s->y[d] = y[k];
+        s->dp[d] = pole_dist(s, y[k]);
         s->ur[d] = ur[k];
         s->ut[d] = ut[k];
         s->up[d] = up[k];
@@ -409,10 +438,10 @@ static double omega_at(const ora_sim *s, double t)
  * reading (dipole exterior, not given in the paper): the l = 2 vacuum
  * potential that matches the corotation surface potential with no net
  * charge, the same rule that yields the paper's monopole exterior. */
-void ora_background(const ora_sim *s, double x, double y, double t, double E[3], double B[3])
+static void background_at(const ora_sim *s, double x, double r, double k, double sn, double t, double E[3],
+                          double B[3])
 {
     E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
-    const double r = f_r(s, x), k = cos_th(s, y), sn = sin_th(s, y);
     const double r0 = s->p.r_in, B0 = s->p.B0;
     const double inv_rl = omega_at(s, t) / s->p.c; /* 1 / R_l */
     switch (s->p.bg_kind) {
@@ -448,6 +477,11 @@ void ora_background(const ora_sim *s, double x, double y, double t, double E[3],
     default:
         break;
     }
+}
+
+void ora_background(const ora_sim *s, double x, double y, double t, double E[3], double B[3])
+{
+    background_at(s, x, f_r(s, x), cos_th(s, y), sin_th(s, y), t, E, B);
 }
 
 /* ------------------------------------------------------------------ */
@@ -765,6 +799,7 @@ static int inject(ora_sim *s, double t_new)
                 const int64_t d = s->n++;
                 s->x[d] = 0.5;
                 s->y[d] = yy;
+                s->dp[d] = pole_dist(s, yy);
                 s->ur[d] = s->ut[d] = s->up[d] = 0.0;
                 s->w[d] = sgn == 0 ? qi : -qi;
                 s->id[d] = 0x8000000000000000ULL | ((uint64_t)s->step << 36) | ((uint64_t)j << 20) |
@@ -785,14 +820,16 @@ static int move_one(const ora_sim *s, int64_t k, double t, fset *F)
 {
     const int nr = s->p.nr, nth = s->p.nth;
     const double x = s->x[k], y = s->y[k], w = s->w[k];
-    const double r = f_r(s, x), kc = cos_th(s, y), sn = sin_th(s, y);
+    const double r = f_r(s, x);
+    double kc, sn;
+    trig_at(s, y, s->dp[k], &kc, &sn);
     double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
     /* particles inside the outer conductor fly ballistically; inside the
      * inner conductor they feel only the corotation field */
     if (x <= nr) {
         double Ea[3], Ba[3];
         if (x >= 0.0) ora_gather(s, x, y, E, B);
-        ora_background(s, x, y, t, Ea, Ba);
+        background_at(s, x, r, kc, sn, t, Ea, Ba);
         for (int a = 0; a < 3; ++a) { E[a] += Ea[a]; B[a] += Ba[a]; }
     }
     /* local basis at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = y */
@@ -815,13 +852,15 @@ static int move_one(const ora_sim *s, int64_t k, double t, fset *F)
     const double ux = cph * un[0] + sph * un[1];
     const double uy = -sph * un[0] + cph * un[1];
     const double uz = un[2];
-    double x1 = x_of_r(s, r1), y1 = y_of(s, k1, s1);
+    const double dp1 = pole_dist_of(s, R1, X[2], r1);
+    double x1 = x_of_r(s, r1), y1 = X[2] >= 0.0 ? dp1 : nth - dp1;
     if (y1 < 0.0) y1 = 0.0;
     if (y1 > nth) y1 = nth;
     if (fabs(x1 - x) >= 1.0 || fabs(y1 - y) >= 1.0) return -1;
     deposit_path(s, F, x, y, x1, y1, w, atan2(sph, cph));
     s->x[k] = x1;
     s->y[k] = y1;
+    s->dp[k] = dp1;
     s->ur[k] = s1 * ux + k1 * uz;
     s->ut[k] = k1 * ux - s1 * uz;
     s->up[k] = uy;
@@ -888,7 +927,7 @@ static int push_particles(ora_sim *s)
     for (int64_t k = 0; k < n; ++k) {
         if (del[k]) { s->n_deleted++; continue; }
         if (m != k) {
-            s->x[m] = s->x[k]; s->y[m] = s->y[k];
+            s->x[m] = s->x[k]; s->y[m] = s->y[k]; s->dp[m] = s->dp[k];
             s->ur[m] = s->ur[k]; s->ut[m] = s->ut[k]; s->up[m] = s->up[k];
             s->w[m] = s->w[k]; s->id[m] = s->id[k];
         }

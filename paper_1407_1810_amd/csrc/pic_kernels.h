@@ -536,13 +536,13 @@ struct GlobalDep {
 // one address.  FP32: nine planes (6 x 4 B fields, 3 x 8 B deposits) plus
 // the work-group's few static bytes within 40 KB, so that four work-groups
 // share a CU's 160 KB; FP64 (two work-groups per CU, as its registers
-// allow): within 80 KB.
+// allow; 6 x 8 B fields, 3 x 8 B + 3 x 4 B deposits): within 80 KB.
 template <typename T>
 constexpr int lds_plane();
 template <>
 constexpr int lds_plane<float>() { return 840; }
 template <>
-constexpr int lds_plane<double>() { return 1120; }
+constexpr int lds_plane<double>() { return 960; }
 
 template <typename T>
 struct LdsView {
@@ -553,43 +553,65 @@ struct LdsView {
     __device__ T geth(int c, int i, int j, T) const { return get(c, i, j); } // mirror staged
 };
 
-// Deposit planes in LDS hold 64-bit fixed point: a contribution v is stored
-// as round(v * scale), so integer LDS atomics (much faster than floating-
-// point ones) accumulate it exactly.  Every contribution is at most max|w|
-// in magnitude.  FP32: scale = 2^30 / max|w|, so one contribution fits an
-// int32 (one hardware conversion) and resolves 1e-9 max|w|, below FP32
-// rounding.  FP64: scale = 2^48 / max|w|, converted exactly with the
-// 1.5 * 2^52 shift (valid below 2^51).  A chunk of at most 4096 particles,
-// each adding at most four contributions to an entry, stays below 2^62.
-template <typename T>
-__device__ __forceinline__ long long to_fixed(T v, T scale);
-template <>
-__device__ __forceinline__ long long to_fixed<float>(float v, float scale)
-{
-    return (long long)(int)__builtin_rintf(v * scale);
-}
-template <>
-__device__ __forceinline__ long long to_fixed<double>(double v, double scale)
-{
-    const double shifted = v * scale + 6755399441055744.0; // 1.5 * 2^52: the integer lands in the low bits
-    return (long long)(__double_as_longlong(shifted) - 0x4338000000000000ll);
-}
+// Deposit planes in LDS hold fixed point, so that integer LDS atomics (much
+// faster than floating-point ones) accumulate the contributions exactly and
+// in any order.  Every contribution v is at most max|w| in magnitude.
+//  FP32: one 64-bit plane per component, v stored as round(v * 2^40 /
+//        max|w|), rounded to the integer through FP64 with the 1.5 * 2^52
+//        shift; the quantum, 1e-12 max|w|, lies below the FP32 rounding of
+//        contributions far smaller than max|w| (small azimuthal steps,
+//        plasma particles beside heavier injected ones).
+//  FP64: x = v * 2^48 / max|w| is split into its nearest integer (a 64-bit
+//        plane, converted exactly with the 1.5 * 2^52 shift, valid below
+//        2^51) and the exact remainder in [-1/2, 1/2] in units of 2^-16 (a
+//        32-bit plane): the quantum is 2^-64 max|w|, far below FP64 rounding
+//        even where the charges of co-located pairs cancel.
+// A chunk of at most 4096 particles adds at most four contributions to an
+// entry: below 2^54 (FP32) or 2^62 (FP64) in the 64-bit planes and 2^31 in
+// the 32-bit ones.
 template <typename T>
 constexpr int fixed_bits();
 template <>
-constexpr int fixed_bits<float>() { return 30; }
+constexpr int fixed_bits<float>() { return 40; }
 template <>
 constexpr int fixed_bits<double>() { return 48; }
+constexpr double kLoScale = 65536.0; // units of the FP64 remainder plane per unit of the main plane
 
 template <typename T>
-struct LdsDep {
-    static constexpr int P = lds_plane<T>();
+struct LdsDep;
+
+template <>
+struct LdsDep<float> {
+    static constexpr int P = lds_plane<float>();
     long long *s;
+    int *lo; // unused in FP32
     int i0, j0, C;
-    T scale;
-    __device__ void add(int c, int i, int j, T v) const
+    float scale;
+    __device__ void add(int c, int i, int j, float v) const
     {
-        atomicAdd((unsigned long long *)&s[c * P + (i - i0) * C + (j - j0)], (unsigned long long)to_fixed(v, scale));
+        const double sh = (double)(v * scale) + 6755399441055744.0; // 1.5 * 2^52
+        const long long q = __double_as_longlong(sh) - 0x4338000000000000ll;
+        atomicAdd((unsigned long long *)&s[c * P + (i - i0) * C + (j - j0)], (unsigned long long)q);
+    }
+};
+
+template <>
+struct LdsDep<double> {
+    static constexpr int P = lds_plane<double>();
+    long long *s;
+    int *lo;
+    int i0, j0, C;
+    double scale;
+    __device__ void add(int c, int i, int j, double v) const
+    {
+        const double x = v * scale;
+        const double sh = x + 6755399441055744.0;                 // 1.5 * 2^52: the integer lands in the low bits
+        const long long hi = __double_as_longlong(sh) - 0x4338000000000000ll;
+        const double rem = x - (sh - 6755399441055744.0);         // exact, |rem| <= 1/2
+        const int r = (int)__builtin_rint(rem * kLoScale);
+        const int e = c * P + (i - i0) * C + (j - j0);
+        atomicAdd((unsigned long long *)&s[e], (unsigned long long)hi);
+        atomicAdd(&lo[e], r);
     }
 };
 
@@ -817,16 +839,22 @@ __device__ inline int wave_max(int v)
 }
 
 // LDS of a push work-group: six field planes of T, then three 64-bit
-// fixed-point deposit planes (8-byte aligned), lds_plane<T>() entries each.
+// fixed-point deposit planes (8-byte aligned), and for FP64 three 32-bit
+// remainder planes, lds_plane<T>() entries each.
 template <typename T>
 __host__ __device__ constexpr size_t lds_field_bytes()
 {
     return ((size_t)6 * lds_plane<T>() * sizeof(T) + 7) / 8 * 8;
 }
 template <typename T>
+__host__ __device__ constexpr size_t lds_dep_bytes()
+{
+    return (size_t)3 * lds_plane<T>() * sizeof(long long);
+}
+template <typename T>
 __host__ __device__ constexpr size_t lds_push_bytes()
 {
-    return lds_field_bytes<T>() + (size_t)3 * lds_plane<T>() * sizeof(long long);
+    return lds_field_bytes<T>() + lds_dep_bytes<T>() + (sizeof(T) == 8 ? (size_t)3 * lds_plane<T>() * sizeof(int) : 0);
 }
 static_assert(lds_push_bytes<float>() + 512 <= 40 * 1024, "FP32 push LDS: four work-groups per CU");
 static_assert(lds_push_bytes<double>() + 512 <= 80 * 1024, "FP64 push LDS: two work-groups per CU");
@@ -890,6 +918,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
         constexpr int P = lds_plane<T>();
         T *sm = reinterpret_cast<T *>(smem_raw);                                  // 6 field planes
         long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>()); // 3 deposit planes
+        int *sl = reinterpret_cast<int *>(smem_raw + lds_field_bytes<T>() + lds_dep_bytes<T>()); // FP64 remainders
         const size_t base = (size_t)(gch - chunk_off[r]) * CH;
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
@@ -946,13 +975,18 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
                 sd[e] = 0;
                 sd[P + e] = 0;
                 sd[2 * P + e] = 0;
+                if constexpr (sizeof(T) == 8) {
+                    sl[e] = 0;
+                    sl[P + e] = 0;
+                    sl[2 * P + e] = 0;
+                }
                 rr += dr;
                 cc += dc;
                 if (cc >= C) { cc -= C; ++rr; }
             }
             __syncthreads();
             const LdsView<T> view{sm, i0, j0, C};
-            const LdsDep<T> dep{sd, i0, j0, C, R.dep_scale};
+            const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const size_t idx = chunk_slot(base, tid, q);
@@ -968,7 +1002,13 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) {
                         const long long v = sd[comp * P + e];
-                        if (v != 0) atomic_add(p.f.c[cFR + comp] + g, (T)v * inv);
+                        if constexpr (sizeof(T) == 8) {
+                            const int l = sl[comp * P + e];
+                            if (v != 0 || l != 0)
+                                atomic_add(p.f.c[cFR + comp] + g, ((T)v + (T)l * (T)(1.0 / kLoScale)) * inv);
+                        } else {
+                            if (v != 0) atomic_add(p.f.c[cFR + comp] + g, (T)v * inv);
+                        }
                     }
                     fr += dr;
                     fc += dc;
