@@ -36,6 +36,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1407_1810_amd", "csrc", f) for f in ("pic_device.h", "pic_kernels.h")]
+PROFILE = os.path.join(ROOT, "profiles", "k_push_dipole_rotator_1024x1024_ppc64.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_counters() -> dict:
+    """Figures of the committed rocprofv3 summary of the push kernel
+    ('key: value' lines), or {} when the kernel sources changed since the
+    counters were taken (then they no longer describe this kernel)."""
+    if not os.path.exists(PROFILE):
+        return {}
+    vals = {}
+    for line in open(PROFILE):
+        if ":" in line and line.startswith("- `"):
+            k, v = line[3:].split("`", 1)[0], line.split(":", 1)[1].strip().rstrip(".")
+            vals[k] = v
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return {}
+    return vals
+
+
 def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt):
     from paper_1407_1810_amd.binding import Sim
     p = cfg["params"]
@@ -209,6 +238,14 @@ def main():
     push_ms = r32["stage_ms"]["push"]
     bytes_launch = PUSH_BYTES["fp32"] * r32["mean_live"] + CELL_BYTES["fp32"] * cells
     achieved = bytes_launch / (push_ms * 1e-3) / 1e9
+    prof = profiled_counters()
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
+    # (scaled by a plain copy of known size), valid for this kernel source
+    traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+    limiter = None
+    if "valu_busy" in prof:
+        limiter = {"unit": "VALU", "busy": float(prof["valu_busy"]),
+                   "valu_instr_per_particle": float(prof["valu_instr_per_particle"])}
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, P)
     out = {
         "metric": "particle-steps/sec (push+deposit+field), FP32 and batched vs FP64 GPU",
@@ -229,8 +266,9 @@ def main():
                    "tile": args.tile, "sort_interval": args.sort_interval, "particles_per_thread": args.ppt,
                    "precision": "fp32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_push<float,{args.ppt}>",
-                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": f"k_push<float,{args.ppt}>",
+                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_launch,
+                     "limiter": limiter},
         "stage_ms": {k: round(v, 5) for k, v in r32["stage_ms"].items()},
         "fp64_gpu": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
