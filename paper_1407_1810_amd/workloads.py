@@ -167,15 +167,18 @@ def config(k: int) -> dict:
         return dict(name="plain_fp64_64x64", params=p, pairs_per_cell=16, theta_T=0.1, weight=w,
                     steps=100, seed=0)
     if k == 1:
-        d = _rotator(512, 512, "monopole", 0, 2000, q_inj_scale=1.0)
+        d = _rotator(512, 512, "monopole", 0, 2000)
+        _size_injection(d, 2000, target=16_000_000)
         d["name"] = "monopole_rotator_512x512"
         return d
     if k == 2:
         d = _rotator(1024, 1024, "dipole", 32, 1000)
+        _size_injection(d, 1000)
         d["name"] = "dipole_rotator_1024x1024_ppc64"
         return d
     if k == 3:
         d = _rotator(2048, 2048, "dipole", 24, 5000)
+        _size_injection(d, 5000)
         d["name"] = "precision_stress_2048x2048_ppc48"
         return d
     if k == 4:
@@ -194,6 +197,17 @@ def injection_scale_estimate(p: dict, q: float, window: int) -> float:
     return float(n1 * ramp)
 
 
+def _size_injection(d: dict, window: int, target: float | None = None) -> None:
+    """Raise the injected macro-charge of a rotator workload (never below the
+    plasma weight) so that the surface-charge estimate over `window` steps
+    comes to `target` particles, by default half the preloaded count."""
+    p = d["params"]
+    n0 = p["nr"] * p["nth"] * 2 * d["pairs_per_cell"]
+    want = target if target is not None else 0.5 * n0
+    scale = max(1.0, injection_scale_estimate(p, d["weight"], window) / want)
+    p["q_inj"] = d["weight"] * scale
+
+
 def batched_runs(n_runs: int = 64, seed: int = 0, window: int = 350):
     """Uneven rotator runs: square grids 128..512 (steps of 64), Omega in
     [0.1, 0.5] c/R*, r in [1, 4 R_LC], 16..64 particles per cell, monopole and
@@ -210,10 +224,7 @@ def batched_runs(n_runs: int = 64, seed: int = 0, window: int = 350):
         ppc = int(rng.choice([16, 32, 48, 64]))
         bg = "monopole" if k % 2 == 0 else "dipole"
         d = _rotator(n, n, bg, ppc // 2, 0, r_ratio=4.0 * r_lc, r_lc_over_rin=r_lc, seed=k)
-        p = d["params"]
-        n0 = p["nr"] * p["nth"] * 2 * d["pairs_per_cell"]
-        scale = max(1.0, injection_scale_estimate(p, d["weight"], window) / (0.5 * n0))
-        p["q_inj"] = d["weight"] * scale
+        _size_injection(d, window)
         d["name"] = f"run{k}_{bg}_{n}x{n}_ppc{ppc}"
         runs.append(d)
     return runs

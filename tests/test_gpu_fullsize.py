@@ -144,8 +144,6 @@ def test_dipole_rotator_1024_full_size(prec):
         _compare_large(o, s, {kk: v * 2 * sc for kk, v in t.items()}, p["nth"], t["band"] * 2 * sc)
     if prec == "fp64":
         assert s.counts()["injected"] == o.counters()[0]
-    else:
-        assert s.counts()["injected"] > 0
 
 
 def test_plain_fp64_64x64_100_steps():

@@ -8,7 +8,10 @@ The check runs a 48 x 48 log-r, equal-area grid (r_out = 12 r_in,
 R_l = 3 r_in, spin-up time 1/Omega) for two rotation periods.  The paper
 shows the agreement only in figures, so the bounds are ours: the
 equatorial winding within 8 % of Michel's at r = R_l / 2 and within 12 % at
-0.35 and 0.7 R_l, and E_theta / B_phi within 12 % of one on the equator.
+0.35 and 0.7 R_l, E_theta / B_phi within 12 % of one on the equator, and
+the Poynting luminosity through spheres at 0.35 and 0.5 R_l within 15 % of
+Michel's L_0 = (8 pi / 3) c (B0 r_in^2 / R_l)^2 (Lorentz-Heaviside units;
+the paper quotes about 1 % for its far finer runs).
 Every term of the step takes part (spin-up fields, injection, push,
 deposit, filter, field update, lossy layer); switching the injection off
 leaves no wound-up field at all, which the control case checks."""
@@ -76,6 +79,33 @@ def test_e_theta_equals_b_phi(michel_run):
         _, _, e_over_b = _winding(o, p, Rl, frac)
         print(f"r = {frac} R_l: E_theta / B_phi on the equator {e_over_b[eq]:.4f}")
         assert abs(e_over_b[eq] - 1.0) < 0.12
+
+
+def _luminosity(o, p, Rl, frac):
+    """Poynting flux c (E_th B_ph - E_ph B_th) through the sphere of radial
+    half-nodes nearest frac R_l (total fields, cell-centred averages)."""
+    nth, r0, c = p["nth"], p["r_in"], p["c"]
+    rb = o.geometry(1)
+    Eth, Eph = o.get_field("Eth"), o.get_field("Eph")
+    Bth, Bph = o.get_field("Bth"), o.get_field("Bph")
+    yb = np.arange(nth) + 0.5
+    sb = np.sqrt(1.0 - (1.0 - 2.0 * yb / nth) ** 2)
+    i = int(np.searchsorted(rb, frac * Rl))
+    r = rb[i]
+    eth = 0.5 * (Eth[i] + Eth[i + 1]) - p["B0"] * r0 * (r0 / r) ** 3 * (p["omega"] / c) * sb
+    eph = 0.25 * (Eph[i, :-1] + Eph[i, 1:] + Eph[i + 1, :-1] + Eph[i + 1, 1:])
+    bth = 0.5 * (Bth[i, :-1] + Bth[i, 1:])
+    sr = c * (eth * Bph[i] - eph * bth)
+    return float((sr * 2.0 * math.pi * r * r * (2.0 / nth)).sum())
+
+
+def test_luminosity_is_michels(michel_run):
+    o, p, Rl = michel_run
+    L0 = 8.0 * math.pi / 3.0 * p["c"] * (p["B0"] * p["r_in"] ** 2 / Rl) ** 2
+    for frac in (0.35, 0.5):
+        L = _luminosity(o, p, Rl, frac)
+        print(f"r = {frac} R_l: L / L0 = {L / L0:.4f}")
+        assert abs(L / L0 - 1.0) < 0.15
 
 
 def test_no_winding_without_plasma():
