@@ -726,13 +726,39 @@ __device__ inline double below_one<double>() { return 0x1.fffffffffffffp-1; }
 
 // One particle: gather, push, move with cancellation-free local increments,
 // deposit, particle boundaries.
+// The stored state of one particle, loaded ahead of its push.
+template <typename T>
+struct PIn {
+    uint32_t c;
+    T fx, fy, w, u0, u1, u2;
+};
+
+template <typename T>
+__device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, size_t idx, unsigned long long n)
+{
+    PIn<T> a;
+    a.c = kDead;
+    a.fx = a.fy = a.w = a.u0 = a.u1 = a.u2 = (T)0;
+    if (idx < n) {
+        a.c = p.cell[idx];
+        a.fx = p.dx[idx];
+        a.fy = p.dy[idx];
+        a.w = p.w[idx];
+        a.u0 = p.ur[idx];
+        a.u1 = p.ut[idx];
+        a.u2 = p.up[idx];
+    }
+    return a;
+}
+
 template <typename T, typename V, typename D>
-__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, size_t idx, uint32_t cl)
+__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, size_t idx, const PIn<T> &in)
 {
     const int nr = p.L.nr, nth = p.L.nth;
+    const uint32_t cl = in.c;
     const int i = cell_i(cl), j = cell_j(cl);
-    const T fx = p.dx[idx], fy = p.dy[idx];
-    const T w = p.w[idx];
+    const T fx = in.fx, fy = in.fy;
+    const T w = in.w;
     T r = p.r_node[i + p.L.G];
     if (p.r_kind == 0) r *= FM<T>::exp(fx * p.dxi);
     else r += fx * p.dxi;
@@ -753,7 +779,7 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
         s = sin(th);
         k = -cos(th);
     }
-    const T u0 = p.ur[idx], u1 = p.ut[idx], u2 = p.up[idx];
+    const T u0 = in.u0, u1 = in.u1, u2 = in.u2;
     // Cartesian frame at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = (0, 1, 0)
     T uc[3] = {s * u0 + k * u1, u2, k * u0 - s * u1};
     const bool outer = i > nr || (i == nr && fx > (T)0); // beyond the outer conductor: ballistic
@@ -987,11 +1013,13 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             __syncthreads();
             const LdsView<T> view{sm, i0, j0, C};
             const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
+            // the next particle's state is loaded while this one is pushed
+            PIn<T> nxt = load_particle(p, chunk_slot(base, tid, 0), n);
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = chunk_slot(base, tid, q);
-                const uint32_t c = idx < n ? p.cell[idx] : kDead;
-                if (c != kDead) push_particle(p, view, dep, idx, c);
+                const PIn<T> cur = nxt;
+                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(base, tid, q + 1), n);
+                if (cur.c != kDead) push_particle(p, view, dep, chunk_slot(base, tid, q), cur);
             }
             __syncthreads();
             {
@@ -1023,8 +1051,8 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const size_t idx = chunk_slot(base, tid, q);
-                const uint32_t c = idx < n ? p.cell[idx] : kDead;
-                if (c != kDead) push_particle(p, view, dep, idx, c);
+                const PIn<T> cur = load_particle(p, idx, n);
+                if (cur.c != kDead) push_particle(p, view, dep, idx, cur);
             }
         }
     }
@@ -1157,6 +1185,11 @@ __global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__
     }
 }
 
+// Windows of 64 particles a wave loads before it works on them: their
+// loads (and, in the scatter, their counter atomics) are in flight together
+// instead of one round trip per window.
+constexpr int kSortBatch = 4;
+
 // Histogram of tile keys.  Within a span the last run of equal keys of each
 // 64-particle window is kept pending and extended by the next window while
 // the key stays the same; a counter is touched only when a run of keys
@@ -1181,29 +1214,40 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
         const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
         int pend_key = -1;          // wave-uniform pending run of keys
         unsigned int pend_len = 0;
-        for (unsigned long long b = s0; b < s1; b += 64) {
-            const unsigned long long idx = b + lane;
-            const int key = idx < s1 ? tm.key(cell[idx]) : INT_MAX;
-            const int prev = __shfl_up(key, 1);
-            const bool head = lane == 0 || key != prev;
-            const unsigned long long heads = __ballot(head);
-            const unsigned long long after = heads & ~lanemask_le(lane);
-            const int next = after ? __ffsll((long long)after) - 1 : 64;
-            const int nruns = __popcll(heads);
-            const int first_key = __shfl(key, 0);
-            const int first_len = nruns > 1 ? __ffsll((long long)(heads & ~1ull)) - 1 : 64;
-            const int last_lane = 63 - __clzll((long long)heads);
-            const int last_key = __shfl(key, last_lane);
-            const bool extend = pend_key == first_key;
-            if (extend) pend_len += (unsigned int)first_len;
-            if (pend_key >= 0 && (!extend || nruns > 1)) { // the pending run has ended
-                if (lane == 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
+        for (unsigned long long bb = s0; bb < s1; bb += 64 * kSortBatch) {
+            uint32_t cw[kSortBatch];
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long idx = bb + 64 * u + lane;
+                cw[u] = idx < s1 ? cell[idx] : 0u;
             }
-            const bool complete = head && lane != last_lane && !(lane == 0 && extend);
-            if (complete && key != INT_MAX) atomic_add(counts + key, (unsigned int)(next - lane));
-            if (!(extend && nruns == 1)) {
-                pend_key = last_key;
-                pend_len = (unsigned int)(64 - last_lane);
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long b = bb + 64 * u;
+                if (b >= s1) break;
+                const unsigned long long idx = b + lane;
+                const int key = idx < s1 ? tm.key(cw[u]) : INT_MAX;
+                const int prev = __shfl_up(key, 1);
+                const bool head = lane == 0 || key != prev;
+                const unsigned long long heads = __ballot(head);
+                const unsigned long long after = heads & ~lanemask_le(lane);
+                const int next = after ? __ffsll((long long)after) - 1 : 64;
+                const int nruns = __popcll(heads);
+                const int first_key = __shfl(key, 0);
+                const int first_len = nruns > 1 ? __ffsll((long long)(heads & ~1ull)) - 1 : 64;
+                const int last_lane = 63 - __clzll((long long)heads);
+                const int last_key = __shfl(key, last_lane);
+                const bool extend = pend_key == first_key;
+                if (extend) pend_len += (unsigned int)first_len;
+                if (pend_key >= 0 && (!extend || nruns > 1)) { // the pending run has ended
+                    if (lane == 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
+                }
+                const bool complete = head && lane != last_lane && !(lane == 0 && extend);
+                if (complete && key != INT_MAX) atomic_add(counts + key, (unsigned int)(next - lane));
+                if (!(extend && nruns == 1)) {
+                    pend_key = last_key;
+                    pend_len = (unsigned int)(64 - last_lane);
+                }
             }
         }
         if (lane == 0 && pend_key >= 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
@@ -1245,8 +1289,10 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
     if (tid == 0) ctr[kLive] = s[1023] - counts[n_keys];
 }
 
-// Stable scatter into the other buffer: each run of equal keys in a
-// 64-particle window claims its slots with one atomic.
+// Scatter into the other buffer: each run of equal keys in a 64-particle
+// window claims its slots with one atomic (kept in particle order within a
+// span).  The keys, the claims and the loads of kSortBatch windows are in
+// flight together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restrict__ runs, int n_runs,
                                                       const unsigned long long *__restrict__ span_off)
@@ -1278,27 +1324,55 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
         const unsigned long long cap = (unsigned long long)R.capacity;
         const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
         const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
-        for (unsigned long long b = s0; b < s1; b += 64) {
-            const unsigned long long idx = b + lane;
-            const uint32_t c = idx < s1 ? cell[idx] : kDead;
-            const int key = idx < s1 ? tm.key(c) : INT_MAX;
-            const int prev = __shfl_up(key, 1);
-            const bool head = lane == 0 || key != prev;
-            const unsigned long long heads = __ballot(head);
-            const unsigned long long after = heads & ~lanemask_le(lane);
-            const int next = after ? __ffsll((long long)after) - 1 : 64;
-            const bool live = key != INT_MAX && key != tm.n_keys;
-            unsigned int got = 0;
-            if (head && live) got = atomic_add_fetch_old(cursor + key, (unsigned int)(next - lane));
-            const int hl = 63 - __clzll((long long)(heads & lanemask_le(lane)));
-            got = __shfl(got, hl);
-            const unsigned long long d = live ? offsets[key] + got + (lane - hl) : 0;
-            if (live && d >= cap) atomic_or(glb(R.status), 4); // never write outside the store
-            if (live && d < cap) {
-                cell_o[d] = c;
+        for (unsigned long long bb = s0; bb < s1; bb += 64 * kSortBatch) {
+            uint32_t cw[kSortBatch];
+            int key[kSortBatch], hl[kSortBatch];
+            unsigned int got[kSortBatch];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) dst[q][d] = src[q][idx];
-                if (id) id_o[d] = id[idx];
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long idx = bb + 64 * u + lane;
+                cw[u] = idx < s1 ? cell[idx] : kDead;
+            }
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long idx = bb + 64 * u + lane;
+                key[u] = idx < s1 ? tm.key(cw[u]) : INT_MAX;
+                const int prev = __shfl_up(key[u], 1);
+                const bool head = lane == 0 || key[u] != prev;
+                const unsigned long long heads = __ballot(head);
+                const unsigned long long after = heads & ~lanemask_le(lane);
+                const int next = after ? __ffsll((long long)after) - 1 : 64;
+                const bool live = key[u] != INT_MAX && key[u] != tm.n_keys;
+                got[u] = 0;
+                if (head && live) got[u] = atomic_add_fetch_old(cursor + key[u], (unsigned int)(next - lane));
+                hl[u] = 63 - __clzll((long long)(heads & lanemask_le(lane)));
+            }
+            // the payloads of all windows are read before any is written
+            T pay[kSortBatch][6];
+            uint64_t pid[kSortBatch];
+            unsigned long long dest[kSortBatch];
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long idx = bb + 64 * u + lane;
+                const bool live = key[u] != INT_MAX && key[u] != tm.n_keys;
+                const unsigned int g = __shfl(got[u], hl[u]);
+                dest[u] = live ? offsets[key[u]] + g + (lane - hl[u]) : ~0ull;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) pay[u][q] = live ? src[q][idx] : (T)0;
+                pid[u] = (live && id) ? id[idx] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const unsigned long long d = dest[u];
+                if (d == ~0ull) continue;
+                if (d >= cap) { // never write outside the store
+                    atomic_or(glb(R.status), 4);
+                    continue;
+                }
+                cell_o[d] = cw[u];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) dst[q][d] = pay[u][q];
+                if (id) id_o[d] = pid[u];
             }
         }
     }
