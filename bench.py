@@ -195,8 +195,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="4x8")
-    ap.add_argument("--sort-interval", type=int, default=8)
-    ap.add_argument("--ppt", type=int, default=8, help="particles per thread of a push work-group (4, 8, 16)")
+    ap.add_argument("--sort-interval", type=int, default=16)
+    ap.add_argument("--ppt", type=int, default=16, help="particles per thread of a push work-group (4, 8, 16)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-runs", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=200)

@@ -90,7 +90,7 @@ typedef struct {
     double sigma_max;         /* sigma* at the outer conductor, eq. (EBcond) */
     int32_t precision;        /* PIC_FP64 | PIC_FP32 */
     int32_t mover;            /* PIC_VAY | PIC_BORIS */
-    int64_t particle_capacity;/* maximum particles held at once */
+    int64_t particle_capacity;/* maximum particles held at once, below 2^31 */
     int32_t tile_r, tile_th;  /* sort tile in cells (0 = 8 x 8) */
     int32_t sort_interval;    /* steps between sorts (0 = 4; < 0 = never) */
     int32_t flags;            /* PIC_FLAG_* */

@@ -734,7 +734,7 @@ struct PIn {
 };
 
 template <typename T>
-__device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, size_t idx, unsigned long long n)
+__device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, uint32_t idx, uint32_t n)
 {
     PIn<T> a;
     a.c = kDead;
@@ -752,7 +752,7 @@ __device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, size_t idx
 }
 
 template <typename T, typename V, typename D>
-__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, size_t idx, const PIn<T> &in)
+__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, uint32_t idx, const PIn<T> &in)
 {
     const int nr = p.L.nr, nth = p.L.nth;
     const uint32_t cl = in.c;
@@ -887,9 +887,11 @@ static_assert(lds_push_bytes<double>() + 512 <= 80 * 1024, "FP64 push LDS: two w
 
 // Slot of iteration q of thread t inside a chunk: each pass of the 256
 // threads reads 256 consecutive particles (full cache lines in and out).
-__device__ __forceinline__ size_t chunk_slot(size_t base, int tid, int q)
+// Particle slots of a run are 32-bit (a store holds below 2^31), so every
+// particle array is addressed from its scalar base with one shared offset.
+__device__ __forceinline__ uint32_t chunk_slot(uint32_t base, int tid, int q)
 {
-    return base + 256 * (size_t)q + tid;
+    return base + 256u * (uint32_t)q + (uint32_t)tid;
 }
 
 
@@ -945,13 +947,14 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
         T *sm = reinterpret_cast<T *>(smem_raw);                                  // 6 field planes
         long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>()); // 3 deposit planes
         int *sl = reinterpret_cast<int *>(smem_raw + lds_field_bytes<T>() + lds_dep_bytes<T>()); // FP64 remainders
-        const size_t base = (size_t)(gch - chunk_off[r]) * CH;
+        const uint32_t base = (uint32_t)(gch - chunk_off[r]) * (uint32_t)CH;
+        const uint32_t n32 = (uint32_t)n;
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = chunk_slot(base, tid, q);
-                const uint32_t c = idx < n ? p.cell[idx] : kDead;
+                const uint32_t idx = chunk_slot(base, tid, q);
+                const uint32_t c = idx < n32 ? p.cell[idx] : kDead;
                 if (c != kDead) {
                     const int ci = cell_i(c), cj = cell_j(c);
                     imin = min(imin, ci); imax = max(imax, ci);
@@ -1014,11 +1017,11 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             const LdsView<T> view{sm, i0, j0, C};
             const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
             // the next particle's state is loaded while this one is pushed
-            PIn<T> nxt = load_particle(p, chunk_slot(base, tid, 0), n);
+            PIn<T> nxt = load_particle(p, chunk_slot(base, tid, 0), n32);
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const PIn<T> cur = nxt;
-                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(base, tid, q + 1), n);
+                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(base, tid, q + 1), n32);
                 if (cur.c != kDead) push_particle(p, view, dep, chunk_slot(base, tid, q), cur);
             }
             __syncthreads();
@@ -1050,8 +1053,8 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
-                const size_t idx = chunk_slot(base, tid, q);
-                const PIn<T> cur = load_particle(p, idx, n);
+                const uint32_t idx = chunk_slot(base, tid, q);
+                const PIn<T> cur = load_particle(p, idx, n32);
                 if (cur.c != kDead) push_particle(p, view, dep, idx, cur);
             }
         }

@@ -1125,7 +1125,8 @@ pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc
         const pic_grid_desc &g = *grid;
         if (g.nr < 2 || g.nth < 4 || g.nth > 8191 || g.nr > 16000 || !(g.r_in > 0) || !(g.r_out > g.r_in) ||
             !(g.c > 0) || g.n_filt < 0 || g.n_filt > 8 || g.absorb_cells < 0 || g.absorb_cells > g.nr ||
-            g.particle_capacity < 0 || (g.precision != PIC_FP64 && g.precision != PIC_FP32) ||
+            g.particle_capacity < 0 || g.particle_capacity > INT32_MAX ||
+            (g.precision != PIC_FP64 && g.precision != PIC_FP32) ||
             (g.mover != PIC_VAY && g.mover != PIC_BORIS) || (g.r_kind != PIC_R_LOG && g.r_kind != PIC_R_LIN) ||
             (g.th_kind != PIC_TH_EQAREA && g.th_kind != PIC_TH_LIN) || g.tile_r < 0 || g.tile_th < 0 ||
             !(g.chunk_ppt == 0 || g.chunk_ppt == 4 || g.chunk_ppt == 8 || g.chunk_ppt == 16))

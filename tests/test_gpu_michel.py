@@ -9,9 +9,11 @@ cylinder, at 0.35, 0.5 and 0.7 R_l:
   * the Poynting luminosity through the sphere within 8 % of
     L_0 = (8 pi / 3) c (B0 r_in^2 / R_l)^2 (Lorentz-Heaviside units; the
     paper quotes about 1 % for its 1024 x 512 run);
-  * E_theta = B_phi on the equator within 12 %.
-The single equatorial row is not gated: it sits in the current sheet and
-fluctuates by 10-15 % from period to period (measured)."""
+  * E_theta = B_phi: the median over the same latitudes of their ratio
+    within 12 %.
+The equatorial row alone is not gated: it sits in the current sheet, and
+its winding and E_theta / B_phi fluctuate by 10-40 % between periods and
+between runs that differ only in floating-point order (measured)."""
 import math
 import sys
 import time
@@ -70,11 +72,8 @@ def _metrics(p, Rl, f, rb, rn, frac):
     bth = 0.5 * (f["Bth"][i, :-1] + f["Bth"][i, 1:])
     L = float((c * (eth_c * f["Bph"][i] - eph * bth) * 2.0 * math.pi * ri * ri * (2.0 / nth)).sum())
     L0 = 8.0 * math.pi / 3.0 * c * (p["B0"] * r0 * r0 / Rl) ** 2
-    k = int(np.searchsorted(rn, ri))
-    eq = nth // 2
-    eth = f["Eth"][k] - p["B0"] * r0 * (r0 / rn[k]) ** 3 * (p["omega"] / c) * sb
-    e_over_b = float(eth[eq] / (0.5 * (f["Bph"][k - 1][eq] + f["Bph"][k][eq])))
-    return lat, L / L0, e_over_b, float(ratio[eq])
+    e_over_b = float(np.median((eth_c / f["Bph"][i])[nth // 8: -nth // 8]))
+    return lat, L / L0, e_over_b, float(ratio[nth // 2])
 
 
 @pytest.mark.parametrize("frac", [0.35, 0.5, 0.7])
