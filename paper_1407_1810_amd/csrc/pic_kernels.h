@@ -510,6 +510,16 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     return p;
 }
 
+// Bilinear interpolation of one staggered lattice from its four values at
+// (i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1), at offsets (x, y).
+template <typename T>
+__device__ __forceinline__ T bilin(T v00, T v10, T v01, T v11, T x, T y)
+{
+    const T lo = v00 + x * (v10 - v00), hi = v01 + x * (v11 - v01);
+    return lo + y * (hi - lo);
+}
+
+// Fields read straight from global memory (chunks not staged in LDS).
 template <typename T>
 struct GlobalView {
     const GFields<T> *f;
@@ -522,13 +532,42 @@ struct GlobalView {
         if (j >= L.nth) return sgn * f->c[c][L.at(i, L.nth - 1)];
         return f->c[c][L.at(i, j)];
     }
+    // Plasma field at offset (fx, fy) of cell (i, j): bilinear in grid
+    // coordinates from each component's own staggered lattice; half-integer-j
+    // components continue across the axis with their parity (r even, theta
+    // and phi odd).
+    __device__ void gather(int i, int j, T fx, T fy, T E[3], T B[3]) const
+    {
+        int ih = i, jh = j;
+        T hx = fx - (T)0.5, hy = fy - (T)0.5;
+        if (hx < (T)0) { ih = i - 1; hx += (T)1; }
+        if (hy < (T)0) { jh = j - 1; hy += (T)1; }
+        E[0] = bilin(get(cER, ih, j), get(cER, ih + 1, j), get(cER, ih, j + 1), get(cER, ih + 1, j + 1), hx, fy);
+        E[1] = bilin(geth(cETH, i, jh, (T)-1), geth(cETH, i + 1, jh, (T)-1), geth(cETH, i, jh + 1, (T)-1),
+                     geth(cETH, i + 1, jh + 1, (T)-1), fx, hy);
+        E[2] = bilin(get(cEPH, i, j), get(cEPH, i + 1, j), get(cEPH, i, j + 1), get(cEPH, i + 1, j + 1), fx, fy);
+        B[0] = bilin(geth(cBR, i, jh, (T)1), geth(cBR, i + 1, jh, (T)1), geth(cBR, i, jh + 1, (T)1),
+                     geth(cBR, i + 1, jh + 1, (T)1), fx, hy);
+        B[1] = bilin(get(cBTH, ih, j), get(cBTH, ih + 1, j), get(cBTH, ih, j + 1), get(cBTH, ih + 1, j + 1), hx, fy);
+        B[2] = bilin(geth(cBPH, ih, jh, (T)-1), geth(cBPH, ih + 1, jh, (T)-1), geth(cBPH, ih, jh + 1, (T)-1),
+                     geth(cBPH, ih + 1, jh + 1, (T)-1), hx, hy);
+    }
 };
 
+// A deposit target gives the entry of node (i, j) (the same in its three
+// face-charge planes), the entry step to node (i + a, j + b), the unit in
+// which charges are added (each particle's charge is scaled to it once) and
+// the add itself.  In global memory: FP atomics on the field arrays.
 template <typename T>
 struct GlobalDep {
+    using Off = long long;
     gptr<T> F[3];
     Layout L;
-    __device__ void add(int c, int i, int j, T v) const { atomic_add(F[c] + L.at(i, j), v); }
+    __device__ Off at(int i, int j) const { return (Off)L.at(i, j); }
+    __device__ Off di() const { return L.pitch; }
+    __device__ Off step(int a, int b) const { return (Off)a * L.pitch + b; }
+    __device__ T unit() const { return (T)1; }
+    __device__ void add(int c, Off e, T v) const { atomic_add(F[c] + e, v); }
 };
 
 // Entries per LDS plane of a push work-group: a compile-time stride, so
@@ -544,13 +583,43 @@ constexpr int lds_plane<float>() { return 840; }
 template <>
 constexpr int lds_plane<double>() { return 960; }
 
+// Entry of node (i, j) in a staged plane of C columns whose first node is
+// (i0, j0); offsets within a work-group's region stay far below 2^23, so
+// the 24-bit multiply (full rate) serves.
+__device__ __forceinline__ int lds_entry(int i, int j, int i0, int j0, int C)
+{
+    return __mul24(i - i0, C) + (j - j0);
+}
+
 template <typename T>
 struct LdsView {
     static constexpr int P = lds_plane<T>();
     const T *s;
     int i0, j0, C;
-    __device__ T get(int c, int i, int j) const { return s[c * P + (i - i0) * C + (j - j0)]; }
-    __device__ T geth(int c, int i, int j, T) const { return get(c, i, j); } // mirror staged
+    // The four values of lattice plane c around entry e, interpolated.
+    __device__ T bilin_at(int c, int e, T x, T y) const
+    {
+        const T *a = s + c * P + e;
+        return bilin(a[0], a[C], a[1], a[C + 1], x, y);
+    }
+    // As GlobalView::gather; the axis mirror was applied when the planes
+    // were staged, and the stencils of the four lattices are reached from
+    // one entry by steps of one row (C) or one column.
+    __device__ void gather(int i, int j, T fx, T fy, T E[3], T B[3]) const
+    {
+        const int e = lds_entry(i, j, i0, j0, C);
+        int ex = e, ey = e; // (i - 1, j) and (i, j - 1) when the half-node lies below
+        T hx = fx - (T)0.5, hy = fy - (T)0.5;
+        if (hx < (T)0) { ex = e - C; hx += (T)1; }
+        if (hy < (T)0) { ey = e - 1; hy += (T)1; }
+        const int exy = ex + (ey - e);
+        E[0] = bilin_at(cER, ex, hx, fy);
+        E[1] = bilin_at(cETH, ey, fx, hy);
+        E[2] = bilin_at(cEPH, e, fx, fy);
+        B[0] = bilin_at(cBR, ey, fx, hy);
+        B[1] = bilin_at(cBTH, ex, hx, fy);
+        B[2] = bilin_at(cBPH, exy, hx, hy);
+    }
 };
 
 // Deposit planes in LDS hold fixed point, so that integer LDS atomics (much
@@ -582,99 +651,71 @@ struct LdsDep;
 
 template <>
 struct LdsDep<float> {
+    using Off = int;
     static constexpr int P = lds_plane<float>();
     long long *s;
     int *lo; // unused in FP32
     int i0, j0, C;
     float scale;
-    __device__ void add(int c, int i, int j, float v) const
+    __device__ int at(int i, int j) const { return lds_entry(i, j, i0, j0, C); }
+    __device__ int di() const { return C; }
+    __device__ int step(int a, int b) const { return __mul24(a, C) + b; }
+    __device__ float unit() const { return scale; }
+    __device__ void add(int c, int e, float v) const
     {
-        const double sh = (double)(v * scale) + 6755399441055744.0; // 1.5 * 2^52
+        const double sh = (double)v + 6755399441055744.0; // 1.5 * 2^52
         const long long q = __double_as_longlong(sh) - 0x4338000000000000ll;
-        atomicAdd((unsigned long long *)&s[c * P + (i - i0) * C + (j - j0)], (unsigned long long)q);
+        atomicAdd((unsigned long long *)&s[c * P + e], (unsigned long long)q);
     }
 };
 
 template <>
 struct LdsDep<double> {
+    using Off = int;
     static constexpr int P = lds_plane<double>();
     long long *s;
     int *lo;
     int i0, j0, C;
     double scale;
-    __device__ void add(int c, int i, int j, double v) const
+    __device__ int at(int i, int j) const { return lds_entry(i, j, i0, j0, C); }
+    __device__ int di() const { return C; }
+    __device__ int step(int a, int b) const { return __mul24(a, C) + b; }
+    __device__ double unit() const { return scale; }
+    __device__ void add(int c, int e, double x) const
     {
-        const double x = v * scale;
         const double sh = x + 6755399441055744.0;                 // 1.5 * 2^52: the integer lands in the low bits
         const long long hi = __double_as_longlong(sh) - 0x4338000000000000ll;
         const double rem = x - (sh - 6755399441055744.0);         // exact, |rem| <= 1/2
         const int r = (int)__builtin_rint(rem * kLoScale);
-        const int e = c * P + (i - i0) * C + (j - j0);
-        atomicAdd((unsigned long long *)&s[e], (unsigned long long)hi);
-        atomicAdd(&lo[e], r);
+        atomicAdd((unsigned long long *)&s[c * P + e], (unsigned long long)hi);
+        atomicAdd(&lo[c * P + e], r);
     }
 };
 
-template <typename T>
-__device__ inline T bilin(T v00, T v10, T v01, T v11, T x, T y)
-{
-    return ((T)1 - y) * (((T)1 - x) * v00 + x * v10) + y * (((T)1 - x) * v01 + x * v11);
-}
-
-// Plasma field at offset (fx, fy) of cell (i, j): bilinear in grid
-// coordinates from each component's own staggered lattice; half-integer-j
-// components continue across the axis with their parity (r even, theta and
-// phi odd).
-template <typename T, typename V>
-__device__ inline void gather(const V &v, int i, int j, T fx, T fy, T E[3], T B[3])
-{
-    int ih = i, jh = j;
-    T hx = fx - (T)0.5, hy = fy - (T)0.5;
-    if (hx < (T)0) { ih = i - 1; hx += (T)1; }
-    if (hy < (T)0) { jh = j - 1; hy += (T)1; }
-    E[0] += bilin(v.get(cER, ih, j), v.get(cER, ih + 1, j), v.get(cER, ih, j + 1), v.get(cER, ih + 1, j + 1), hx, fy);
-    E[1] += bilin(v.geth(cETH, i, jh, (T)-1), v.geth(cETH, i + 1, jh, (T)-1), v.geth(cETH, i, jh + 1, (T)-1),
-                  v.geth(cETH, i + 1, jh + 1, (T)-1), fx, hy);
-    E[2] += bilin(v.get(cEPH, i, j), v.get(cEPH, i + 1, j), v.get(cEPH, i, j + 1), v.get(cEPH, i + 1, j + 1), fx, fy);
-    B[0] += bilin(v.geth(cBR, i, jh, (T)1), v.geth(cBR, i + 1, jh, (T)1), v.geth(cBR, i, jh + 1, (T)1),
-                  v.geth(cBR, i + 1, jh + 1, (T)1), fx, hy);
-    B[1] += bilin(v.get(cBTH, ih, j), v.get(cBTH, ih + 1, j), v.get(cBTH, ih, j + 1), v.get(cBTH, ih + 1, j + 1), hx, fy);
-    B[2] += bilin(v.geth(cBPH, ih, jh, (T)-1), v.geth(cBPH, ih + 1, jh, (T)-1), v.geth(cBPH, ih, jh + 1, (T)-1),
-                  v.geth(cBPH, ih + 1, jh + 1, (T)-1), hx, hy);
-}
-
-// Charge flux of a cell-sized cloud moving on a straight piece inside cell
-// (i, j), local coordinates (xa, ya) -> (xb, yb): the integral of the
-// bilinear weights along the piece.
+// Charge flux of a cell-sized cloud moving on a straight piece (xa, ya) ->
+// (xb, yb) inside the cell whose first node is entry e, at grid offset
+// (ox, oy) from the frame of the coordinates: the integral of the bilinear
+// weights along the piece.
 template <typename T, typename D>
-__device__ inline void vb_piece(const D &d, int i, int j, T xa, T ya, T xb, T yb, T Q)
+__device__ __forceinline__ void vb_piece(const D &d, typename D::Off e, T xa, T ya, T xb, T yb, T ox, T oy, T Q)
 {
-    const T mx = (T)0.5 * (xa + xb), my = (T)0.5 * (ya + yb);
+    const T mx = (T)0.5 * (xa + xb) - ox, my = (T)0.5 * (ya + yb) - oy;
     const T qx = Q * (xb - xa), qy = Q * (yb - ya);
-    d.add(0, i, j, qx * ((T)1 - my));
-    d.add(0, i, j + 1, qx * my);
-    d.add(1, i, j, qy * ((T)1 - mx));
-    d.add(1, i + 1, j, qy * mx);
-}
-
-// One straight piece of a move, in the frame of cell (i, j): deposited in
-// the cell that holds its midpoint (the last row of cells takes y = nth).
-template <typename T, typename D>
-__device__ __forceinline__ void vb_segment(const D &d, int i, int j, int nth, T xa, T ya, T xb, T yb, T Q)
-{
-    const T mx = (T)0.5 * (xa + xb), my = (T)0.5 * (ya + yb);
-    const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
-    int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
-    if (j + dj > nth - 1) dj = nth - 1 - j;
-    vb_piece(d, i + di, j + dj, xa - (T)di, ya - (T)dj, xb - (T)di, yb - (T)dj, Q);
+    const T ax = qx * my, ay = qy * mx;
+    d.add(0, e, qx - ax);
+    d.add(0, e + 1, ax);
+    d.add(1, e, qy - ay);
+    d.add(1, e + d.di(), ay);
 }
 
 // Villasenor-Buneman deposit of the move (x0, y0) -> (x1, y1), both in the
 // frame of cell (i, j) (start in [0,1)^2, end within one cell of it): cut at
-// the cell faces it crosses (at most two), in the order met along the
-// path, each piece deposited in its own cell; plus the ring charge
-// Q dphi / 2 pi crossing a meridional half-plane, assigned bilinearly at the
-// midpoint of the move.
+// the cell faces it crosses (at most one per axis), in the order met along
+// the path; the first piece lies in cell (i, j), the last in the end cell
+// (i + cx, j + cy), a middle one in the cell entered at the first crossing.
+// Plus the ring charge Q dphi / 2 pi crossing a meridional half-plane,
+// assigned bilinearly at the midpoint of the move.  The last row of cells
+// holds y = nth.  Q is in the target's unit.
 template <typename T, typename D>
 __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0, T x1, T y1, T Q, T dphi)
 {
@@ -682,16 +723,17 @@ __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0,
     T X = 0, Y = 0;
     if (x1 >= (T)1) { cx = 1; X = (T)1; } else if (x1 < (T)0) { cx = -1; X = (T)0; }
     if (y1 >= (T)1 && j < nth - 1) { cy = 1; Y = (T)1; } else if (y1 < (T)0) { cy = -1; Y = (T)0; }
-    // split points s1, s2 (n of them) between the start and the end
-    int n = 0;
+    // split points s1, s2 (n of them) between the start and the end; the
+    // middle piece lies in cell (i + a, j + b)
+    int n = 0, a = cx, b = cy;
     T s1x = x1, s1y = y1, s2x = x1, s2y = y1;
     if (cx && cy) {
         const T tx = FM<T>::div(X - x0, x1 - x0), ty = FM<T>::div(Y - y0, y1 - y0);
         const T yx = y0 + tx * (y1 - y0), xy = x0 + ty * (x1 - x0);
         if (tx < ty) {
-            s1x = X; s1y = yx; s2x = xy; s2y = Y; n = 2;
+            s1x = X; s1y = yx; s2x = xy; s2y = Y; b = 0; n = 2;
         } else if (ty < tx) {
-            s1x = xy; s1y = Y; s2x = X; s2y = yx; n = 2;
+            s1x = xy; s1y = Y; s2x = X; s2y = yx; a = 0; n = 2;
         } else {
             s1x = X; s1y = Y; n = 1;
         }
@@ -702,19 +744,23 @@ __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0,
         const T ty = FM<T>::div(Y - y0, y1 - y0);
         s1x = x0 + ty * (x1 - x0); s1y = Y; n = 1;
     }
-    vb_segment(d, i, j, nth, x0, y0, s1x, s1y, Q);
-    if (n >= 1) vb_segment(d, i, j, nth, s1x, s1y, s2x, s2y, Q);
-    if (n >= 2) vb_segment(d, i, j, nth, s2x, s2y, x1, y1, Q);
+    const typename D::Off e = d.at(i, j);
+    vb_piece(d, e, x0, y0, s1x, s1y, (T)0, (T)0, Q);
+    if (n >= 1) vb_piece(d, e + d.step(a, b), s1x, s1y, s2x, s2y, (T)a, (T)b, Q);
+    if (n >= 2) vb_piece(d, e + d.step(cx, cy), s2x, s2y, x1, y1, (T)cx, (T)cy, Q);
     const T mx = (T)0.5 * (x0 + x1), my = (T)0.5 * (y0 + y1);
-    const int di = mx >= (T)1 ? 1 : (mx < (T)0 ? -1 : 0);
-    int dj = my >= (T)1 ? 1 : (my < (T)0 ? -1 : 0);
-    if (j + dj > nth - 1) dj = nth - 1 - j;
-    const T fx = mx - (T)di, fy = my - (T)dj;
+    const T ci = floor(mx);
+    T cj = floor(my);
+    if (j + (int)cj > nth - 1) cj = (T)(nth - 1 - j);
+    const T fx = mx - ci, fy = my - cj;
     const T q = Q * dphi * (T)(0.5 / kPi);
-    d.add(2, i + di, j + dj, q * ((T)1 - fx) * ((T)1 - fy));
-    d.add(2, i + di + 1, j + dj, q * fx * ((T)1 - fy));
-    d.add(2, i + di, j + dj + 1, q * ((T)1 - fx) * fy);
-    d.add(2, i + di + 1, j + dj + 1, q * fx * fy);
+    const T q1 = q * fy, q0 = q - q1;                   // rows j and j + 1 of the cell
+    const T a0 = q0 * fx, a1 = q1 * fx;
+    const typename D::Off er = e + d.step((int)ci, (int)cj);
+    d.add(2, er, q0 - a0);
+    d.add(2, er + d.di(), a0);
+    d.add(2, er + 1, q1 - a1);
+    d.add(2, er + d.di() + 1, a1);
 }
 
 template <typename T>
@@ -787,8 +833,12 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     const T eps = w > (T)0 ? p.eps0 : (w < (T)0 ? -p.eps0 : (T)0);
     T ig; // 1 / gamma of the new momentum
     if (!outer && eps != (T)0) {
-        T E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-        if (!inner) gather(view, i, j, fx, fy, E, B);
+        T E[3], B[3];
+        if (!inner) {
+            view.gather(i, j, fx, fy, E, B);
+        } else {
+            E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = (T)0;
+        }
         add_background(p.bg, p.inv_rl, inner, r, ir, k, s, E, B);
         const T Ec[3] = {s * E[0] + k * E[1], E[2], k * E[0] - s * E[1]};
         const T Bc[3] = {s * B[0] + k * B[1], B[2], k * B[0] - s * B[1]};
@@ -829,7 +879,7 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
         cph = xs * iR;
         sph = ey * iR;
     }
-    vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w, FM<T>::atan2(sph, cph));
+    vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w * dep.unit(), FM<T>::atan2(sph, cph));
     const T k1 = zs * isq, s1 = Rn * isq;
     const T ux = cph * uc[0] + sph * uc[1], uy = -sph * uc[0] + cph * uc[1], uz = uc[2];
     int ni = i, nj = j;
