@@ -467,12 +467,12 @@ struct PushArgs {
     int r_kind, th_kind, mover, n_filt;
     T c, dxi, inv_dxi, nth_f, two_over_nth, pi_over_nth, inv_pi_over_nth, eps0, inv_rl;
     gptr<const T> r_node; // r(i) at [i + G]
-    gptr<const T> k_node; // cos theta_j
     gptr<uint32_t> cell;
     gptr<T> dx, dy, ur, ut, up;
     gptr<const T> w;
     gptr<unsigned long long> n_dead;
     gptr<int> status;
+    uint32_t sink;        // spare slot past the capacity: stores of lanes without a particle
 };
 
 template <typename T>
@@ -497,7 +497,6 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     p.eps0 = R.eps0;
     p.inv_rl = (T)inv_light_cylinder(R.omega, R.t_spin, R.cd, step);
     p.r_node = glb(R.m.r_node);
-    p.k_node = glb(R.m.k);
     p.cell = glb(R.cell[cur]);
     p.dx = glb(R.arr[cur][0]);
     p.dy = glb(R.arr[cur][1]);
@@ -507,6 +506,7 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     p.w = glb((const T *)R.arr[cur][5]);
     p.n_dead = glb(R.ctr + kDeadSinceSort);
     p.status = glb(R.status);
+    p.sink = (uint32_t)R.capacity;
     return p;
 }
 
@@ -524,6 +524,8 @@ template <typename T>
 struct GlobalView {
     const GFields<T> *f;
     Layout L;
+    gptr<const T> rn; // r(i) at [i + G]
+    __device__ T r_node(int i) const { return rn[i + L.G]; }
     __device__ T get(int c, int i, int j) const { return f->c[c][L.at(i, j)]; }
     // half-integer-j component continued across the axis with parity sgn
     __device__ T geth(int c, int i, int j, T sgn) const
@@ -572,16 +574,18 @@ struct GlobalDep {
 
 // Entries per LDS plane of a push work-group: a compile-time stride, so
 // that every plane of one (i, j) is reached with an immediate offset from
-// one address.  FP32: nine planes (6 x 4 B fields, 3 x 8 B deposits) plus
-// the work-group's few static bytes within 40 KB, so that four work-groups
-// share a CU's 160 KB; FP64 (two work-groups per CU, as its registers
-// allow; 6 x 8 B fields, 3 x 8 B + 3 x 4 B deposits): within 80 KB.
+// one address.  FP32: nine planes (6 x 4 B fields, 3 x 8 B deposits), the
+// radii of the region's rows and the work-group's few static bytes within
+// 40 KB, so that four work-groups share a CU's 160 KB; FP64 (two
+// work-groups per CU, as its registers allow; 6 x 8 B fields, 3 x 8 B +
+// 3 x 4 B deposits): within 80 KB.
 template <typename T>
 constexpr int lds_plane();
 template <>
-constexpr int lds_plane<float>() { return 840; }
+constexpr int lds_plane<float>() { return 832; }
 template <>
-constexpr int lds_plane<double>() { return 960; }
+constexpr int lds_plane<double>() { return 956; }
+constexpr int kLdsRows = 128; // most rows of a staged region
 
 // Entry of node (i, j) in a staged plane of C columns whose first node is
 // (i0, j0); offsets within a work-group's region stay far below 2^23, so
@@ -595,7 +599,9 @@ template <typename T>
 struct LdsView {
     static constexpr int P = lds_plane<T>();
     const T *s;
+    const T *rn; // r(i) of the region's rows at [i - i0]
     int i0, j0, C;
+    __device__ T r_node(int i) const { return rn[i - i0]; }
     // The four values of lattice plane c around entry e, interpolated.
     __device__ T bilin_at(int c, int e, T x, T y) const
     {
@@ -770,13 +776,17 @@ __device__ inline float below_one<float>() { return 0x1.fffffep-1f; }
 template <>
 __device__ inline double below_one<double>() { return 0x1.fffffffffffffp-1; }
 
-// One particle: gather, push, move with cancellation-free local increments,
-// deposit, particle boundaries.
-// The stored state of one particle, loaded ahead of its push.
+// The stored state of one particle, loaded ahead of its push, and the
+// state it leaves.
 template <typename T>
 struct PIn {
     uint32_t c;
     T fx, fy, w, u0, u1, u2;
+};
+template <typename T>
+struct POut {
+    uint32_t c;
+    T fx, fy, u0, u1, u2;
 };
 
 template <typename T>
@@ -797,15 +807,33 @@ __device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, uint32_t i
     return a;
 }
 
+// Every iteration of the push stores one state per lane (a lane without a
+// particle writes the spare slot), so that the loop issues the same memory
+// operations on every path and the wait for the next particle's loads,
+// issued before these stores, never waits for the stores.
+template <typename T>
+__device__ __forceinline__ void store_particle(const PushArgs<T> &p, uint32_t idx, const POut<T> &o)
+{
+    p.dx[idx] = o.fx;
+    p.dy[idx] = o.fy;
+    p.ur[idx] = o.u0;
+    p.ut[idx] = o.u1;
+    p.up[idx] = o.u2;
+    p.cell[idx] = o.c;
+}
+
+// One particle: gather, push, move with cancellation-free local increments,
+// deposit, particle boundaries; returns the new state (the old one if the
+// move breaks the CFL bound, which is flagged).
 template <typename T, typename V, typename D>
-__device__ inline void push_particle(const PushArgs<T> &p, const V &view, const D &dep, uint32_t idx, const PIn<T> &in)
+__device__ inline POut<T> push_particle(const PushArgs<T> &p, const V &view, const D &dep, const PIn<T> &in)
 {
     const int nr = p.L.nr, nth = p.L.nth;
     const uint32_t cl = in.c;
     const int i = cell_i(cl), j = cell_j(cl);
     const T fx = in.fx, fy = in.fy;
     const T w = in.w;
-    T r = p.r_node[i + p.L.G];
+    T r = view.r_node(i);
     if (p.r_kind == 0) r *= FM<T>::exp(fx * p.dxi);
     else r += fx * p.dxi;
     const T ir = FM<T>::rcp(r);
@@ -814,7 +842,8 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
         // sin theta = (2/nth) sqrt(y (nth - y)); both factors formed from the
         // cell index and the offset so that neither cancels near a pole
         const T ys = (T)j + fy, yn = (T)(nth - j) - fy;
-        k = p.k_node[j] - fy * p.two_over_nth;
+        // cos theta = 1 - 2 y / nth, from the node value 1 - 2 j / nth (one rounding)
+        k = fma(-fy, p.two_over_nth, fma(-(T)j, p.two_over_nth, (T)1));
         s = p.two_over_nth * FM<T>::sqrt(fmax(ys * yn, (T)0));
     } else if (2 * j < nth) {
         const T th = ((T)j + fy) * p.pi_over_nth;
@@ -872,7 +901,7 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     if (Y1 > (T)(nth - j)) Y1 = (T)(nth - j);
     if (!(fabs(X1 - fx) < (T)1 && fabs(Y1 - fy) < (T)1)) { // CFL (or a non-finite value)
         atomic_or(p.status, 1);
-        return;
+        return POut<T>{in.c, in.fx, in.fy, in.u0, in.u1, in.u2};
     }
     T cph = (T)1, sph = (T)0;
     if (Rn > (T)0) {
@@ -889,18 +918,20 @@ __device__ inline void push_particle(const PushArgs<T> &p, const V &view, const 
     if (ny >= (T)1) { ++nj; ny -= (T)1; }
     else if (ny < (T)0) { --nj; ny += (T)1; if (ny >= (T)1) ny = below_one<T>(); }
     if (nj > nth - 1) { nj = nth - 1; ny = (T)1; }      // y' = nth belongs to the last cell
-    p.dx[idx] = nx;
-    p.dy[idx] = ny;
-    p.ur[idx] = s1 * ux + k1 * uz;
-    p.ut[idx] = k1 * ux - s1 * uz;
-    p.up[idx] = uy;
+    POut<T> o;
+    o.fx = nx;
+    o.fy = ny;
+    o.u0 = s1 * ux + k1 * uz;
+    o.u1 = k1 * ux - s1 * uz;
+    o.u2 = uy;
     const int lim = p.n_filt + 1;                        // whole filtered shape inside a conductor
     if (ni < -lim || ni > nr + lim || (ni == nr + lim && nx > (T)0)) {
-        p.cell[idx] = kDead;
+        o.c = kDead;
         atomic_add(p.n_dead, 1ull);
     } else {
-        p.cell[idx] = pack_cell(ni, nj);
+        o.c = pack_cell(ni, nj);
     }
+    return o;
 }
 
 __device__ inline int wave_min(int v)
@@ -914,13 +945,19 @@ __device__ inline int wave_max(int v)
     return v;
 }
 
-// LDS of a push work-group: six field planes of T, then three 64-bit
-// fixed-point deposit planes (8-byte aligned), and for FP64 three 32-bit
-// remainder planes, lds_plane<T>() entries each.
+// LDS of a push work-group: six field planes of T, the radii of the
+// region's rows, then three 64-bit fixed-point deposit planes (8-byte
+// aligned), and for FP64 three 32-bit remainder planes, lds_plane<T>()
+// entries each.
+template <typename T>
+__host__ __device__ constexpr size_t lds_rows_offset()
+{
+    return (size_t)6 * lds_plane<T>() * sizeof(T);
+}
 template <typename T>
 __host__ __device__ constexpr size_t lds_field_bytes()
 {
-    return ((size_t)6 * lds_plane<T>() * sizeof(T) + 7) / 8 * 8;
+    return (lds_rows_offset<T>() + (size_t)kLdsRows * sizeof(T) + 7) / 8 * 8;
 }
 template <typename T>
 __host__ __device__ constexpr size_t lds_dep_bytes()
@@ -995,6 +1032,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
         const int nth = p.L.nth;
         constexpr int P = lds_plane<T>();
         T *sm = reinterpret_cast<T *>(smem_raw);                                  // 6 field planes
+        T *srn = reinterpret_cast<T *>(smem_raw + lds_rows_offset<T>());          // radii of the rows
         long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>()); // 3 deposit planes
         int *sl = reinterpret_cast<int *>(smem_raw + lds_field_bytes<T>() + lds_dep_bytes<T>()); // FP64 remainders
         const uint32_t base = (uint32_t)(gch - chunk_off[r]) * (uint32_t)CH;
@@ -1027,7 +1065,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             if (imin <= imax) {
                 const int Rr = imax - imin + 4;
                 C = jmax - jmin + 4;
-                use = (long long)Rr * C <= cap;
+                use = (long long)Rr * C <= cap && Rr <= kLdsRows;
                 i0 = imin - 1;
                 j0 = jmin - 1;
             }
@@ -1063,16 +1101,20 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
                 cc += dc;
                 if (cc >= C) { cc -= C; ++rr; }
             }
+            for (int e = tid; e < imax - imin + 4; e += 256) srn[e] = p.r_node[i0 + e + p.L.G];
             __syncthreads();
-            const LdsView<T> view{sm, i0, j0, C};
+            const LdsView<T> view{sm, srn, i0, j0, C};
             const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
             // the next particle's state is loaded while this one is pushed
             PIn<T> nxt = load_particle(p, chunk_slot(base, tid, 0), n32);
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const PIn<T> cur = nxt;
+                const uint32_t idx = chunk_slot(base, tid, q);
                 if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(base, tid, q + 1), n32);
-                if (cur.c != kDead) push_particle(p, view, dep, chunk_slot(base, tid, q), cur);
+                POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
+                if (cur.c != kDead) o = push_particle(p, view, dep, cur);
+                store_particle(p, idx < n32 ? idx : p.sink, o);
             }
             __syncthreads();
             {
@@ -1099,13 +1141,15 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             __syncthreads();
         } else {
             if (tid == 0 && cap > 0) atomic_add(glb(R.ctr + kGlobalChunks), 1ull);
-            const GlobalView<T> view{&p.f, p.L};
+            const GlobalView<T> view{&p.f, p.L, p.r_node};
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
                 const uint32_t idx = chunk_slot(base, tid, q);
                 const PIn<T> cur = load_particle(p, idx, n32);
-                if (cur.c != kDead) push_particle(p, view, dep, idx, cur);
+                POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
+                if (cur.c != kDead) o = push_particle(p, view, dep, cur);
+                store_particle(p, idx < n32 ? idx : p.sink, o);
             }
         }
     }
