@@ -472,7 +472,6 @@ struct PushArgs {
     gptr<const T> w;
     gptr<unsigned long long> n_dead;
     gptr<int> status;
-    uint32_t sink;        // spare slot past the capacity: stores of lanes without a particle
 };
 
 template <typename T>
@@ -506,7 +505,6 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     p.w = glb((const T *)R.arr[cur][5]);
     p.n_dead = glb(R.ctr + kDeadSinceSort);
     p.status = glb(R.status);
-    p.sink = (uint32_t)R.capacity;
     return p;
 }
 
@@ -776,6 +774,20 @@ __device__ inline float below_one<float>() { return 0x1.fffffep-1f; }
 template <>
 __device__ inline double below_one<double>() { return 0x1.fffffffffffffp-1; }
 
+// Element k of a particle array addressed from the chunk's first slot: a
+// scalar base plus a 32-bit byte offset, the form of a global access with
+// a scalar base (chunks are far below 4 GiB).
+template <typename U>
+__device__ __forceinline__ auto &at_slot(gptr<U> a, uint32_t k)
+{
+    return *(gptr<U>)((gptr<char>)a + k * (uint32_t)sizeof(U));
+}
+template <typename U>
+__device__ __forceinline__ U at_slot(gptr<const U> a, uint32_t k)
+{
+    return *(gptr<const U>)((gptr<const char>)a + k * (uint32_t)sizeof(U));
+}
+
 // The stored state of one particle, loaded ahead of its push, and the
 // state it leaves.
 template <typename T>
@@ -796,30 +808,31 @@ __device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, uint32_t i
     a.c = kDead;
     a.fx = a.fy = a.w = a.u0 = a.u1 = a.u2 = (T)0;
     if (idx < n) {
-        a.c = p.cell[idx];
-        a.fx = p.dx[idx];
-        a.fy = p.dy[idx];
-        a.w = p.w[idx];
-        a.u0 = p.ur[idx];
-        a.u1 = p.ut[idx];
-        a.u2 = p.up[idx];
+        a.c = at_slot(p.cell, idx);
+        a.fx = at_slot(p.dx, idx);
+        a.fy = at_slot(p.dy, idx);
+        a.w = at_slot(p.w, idx);
+        a.u0 = at_slot(p.ur, idx);
+        a.u1 = at_slot(p.ut, idx);
+        a.u2 = at_slot(p.up, idx);
     }
     return a;
 }
 
-// Every iteration of the push stores one state per lane (a lane without a
-// particle writes the spare slot), so that the loop issues the same memory
-// operations on every path and the wait for the next particle's loads,
-// issued before these stores, never waits for the stores.
+// Every iteration of the push stores one state per lane (a lane past the
+// run's last particle writes its own slot, inside the chunk of spare slots
+// every particle array holds past the capacity), so that the loop issues
+// the same memory operations on every path and the wait for the next
+// particle's loads, issued before these stores, never waits for the stores.
 template <typename T>
 __device__ __forceinline__ void store_particle(const PushArgs<T> &p, uint32_t idx, const POut<T> &o)
 {
-    p.dx[idx] = o.fx;
-    p.dy[idx] = o.fy;
-    p.ur[idx] = o.u0;
-    p.ut[idx] = o.u1;
-    p.up[idx] = o.u2;
-    p.cell[idx] = o.c;
+    at_slot(p.dx, idx) = o.fx;
+    at_slot(p.dy, idx) = o.fy;
+    at_slot(p.ur, idx) = o.u0;
+    at_slot(p.ut, idx) = o.u1;
+    at_slot(p.up, idx) = o.u2;
+    at_slot(p.cell, idx) = o.c;
 }
 
 // One particle: gather, push, move with cancellation-free local increments,
@@ -974,11 +987,27 @@ static_assert(lds_push_bytes<double>() + 512 <= 80 * 1024, "FP64 push LDS: two w
 
 // Slot of iteration q of thread t inside a chunk: each pass of the 256
 // threads reads 256 consecutive particles (full cache lines in and out).
-// Particle slots of a run are 32-bit (a store holds below 2^31), so every
-// particle array is addressed from its scalar base with one shared offset.
-__device__ __forceinline__ uint32_t chunk_slot(uint32_t base, int tid, int q)
+// The particle arrays are addressed from the chunk's first slot (a scalar
+// base) with this small per-lane offset.
+__device__ __forceinline__ uint32_t chunk_slot(int tid, int q)
 {
-    return base + 256u * (uint32_t)q + (uint32_t)tid;
+    return 256u * (uint32_t)q + (uint32_t)tid;
+}
+
+// Most particles of one push chunk (256 threads x 16); every particle array
+// holds this many spare slots past its capacity.
+constexpr int kMaxChunk = 256 * 16;
+
+template <typename T>
+__device__ __forceinline__ void at_chunk(PushArgs<T> &p, uint32_t base)
+{
+    p.cell += base;
+    p.dx += base;
+    p.dy += base;
+    p.ur += base;
+    p.ut += base;
+    p.up += base;
+    p.w += base;
 }
 
 
@@ -1027,7 +1056,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
         const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
         const unsigned long long n = ctr[kTotal];
         const int cur = (int)ctr[kCur];
-        const PushArgs<T> p = push_args(R, cur, (double)ctr[kStep]);
+        PushArgs<T> p = push_args(R, cur, (double)ctr[kStep]);
         const int cap = R.lds_cap;
         const int nth = p.L.nth;
         constexpr int P = lds_plane<T>();
@@ -1035,14 +1064,16 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
         T *srn = reinterpret_cast<T *>(smem_raw + lds_rows_offset<T>());          // radii of the rows
         long long *sd = reinterpret_cast<long long *>(smem_raw + lds_field_bytes<T>()); // 3 deposit planes
         int *sl = reinterpret_cast<int *>(smem_raw + lds_field_bytes<T>() + lds_dep_bytes<T>()); // FP64 remainders
+        static_assert(CH <= kMaxChunk, "push chunk larger than the spare slots");
         const uint32_t base = (uint32_t)(gch - chunk_off[r]) * (uint32_t)CH;
-        const uint32_t n32 = (uint32_t)n;
+        at_chunk(p, base);
+        const uint32_t n32 = (uint32_t)min(n - base, (unsigned long long)CH); // particles of this chunk
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
         if (cap > 0) {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                const uint32_t idx = chunk_slot(base, tid, q);
-                const uint32_t c = idx < n32 ? p.cell[idx] : kDead;
+                const uint32_t idx = chunk_slot(tid, q);
+                const uint32_t c = idx < n32 ? at_slot(p.cell, idx) : kDead;
                 if (c != kDead) {
                     const int ci = cell_i(c), cj = cell_j(c);
                     imin = min(imin, ci); imax = max(imax, ci);
@@ -1106,15 +1137,18 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             const LdsView<T> view{sm, srn, i0, j0, C};
             const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
             // the next particle's state is loaded while this one is pushed
-            PIn<T> nxt = load_particle(p, chunk_slot(base, tid, 0), n32);
+            PIn<T> nxt = load_particle(p, chunk_slot(tid, 0), n32);
 #pragma unroll 1
-            for (int q = 0; q < PPT; ++q) {
+            for (int q0 = 0; q0 < PPT; ++q0) {
+                // the iteration index, opaque to the compiler, so that it does
+                // not turn the seven array accesses into seven 64-bit pointers
+                const int q = __builtin_amdgcn_readfirstlane(q0);
                 const PIn<T> cur = nxt;
-                const uint32_t idx = chunk_slot(base, tid, q);
-                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(base, tid, q + 1), n32);
+                const uint32_t idx = chunk_slot(tid, q);
+                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(tid, q + 1), n32);
                 POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
                 if (cur.c != kDead) o = push_particle(p, view, dep, cur);
-                store_particle(p, idx < n32 ? idx : p.sink, o);
+                store_particle(p, idx, o);
             }
             __syncthreads();
             {
@@ -1144,12 +1178,13 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             const GlobalView<T> view{&p.f, p.L, p.r_node};
             const GlobalDep<T> dep{{p.f.c[cFR], p.f.c[cFTH], p.f.c[cFPH]}, p.L};
 #pragma unroll 1
-            for (int q = 0; q < PPT; ++q) {
-                const uint32_t idx = chunk_slot(base, tid, q);
+            for (int q0 = 0; q0 < PPT; ++q0) {
+                const int q = __builtin_amdgcn_readfirstlane(q0);
+                const uint32_t idx = chunk_slot(tid, q);
                 const PIn<T> cur = load_particle(p, idx, n32);
                 POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
                 if (cur.c != kDead) o = push_particle(p, view, dep, cur);
-                store_particle(p, idx < n32 ? idx : p.sink, o);
+                store_particle(p, idx, o);
             }
         }
     }

@@ -466,12 +466,12 @@ public:
         R.t_spin = ph.t_spin;
         R.cd = gd.c;
         for (int s = 0; s < 2; ++s) {
-            // one spare slot past the capacity takes the push's stores of
-            // lanes without a particle
-            cell_[s] = dalloc<uint32_t>(cap_ + 1);
+            // one push chunk of spare slots past the capacity takes the
+            // stores of lanes past the last particle
+            cell_[s] = dalloc<uint32_t>(cap_ + kMaxChunk);
             R.cell[s] = cell_[s];
             for (int a = 0; a < 6; ++a) {
-                arr_[s][a] = dalloc<T>(cap_ + 1);
+                arr_[s][a] = dalloc<T>(cap_ + kMaxChunk);
                 R.arr[s][a] = arr_[s][a];
             }
             id_[s] = with_ids_ ? dalloc<uint64_t>(std::max<int64_t>(cap_, 1)) : nullptr;
