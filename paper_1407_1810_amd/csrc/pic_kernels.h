@@ -1294,12 +1294,25 @@ __device__ inline unsigned long long lanemask_le(int lane)
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
 
-// Particles per wave of the sort kernels: each wave walks a contiguous span
-// of one run so that the particles of one tile (kept together by the
-// previous sort) are counted and placed by about one wave, not by dozens
-// contending for the same counter.  The spans of all sorting runs are laid
-// end to end (prefix span_off).
-constexpr int kSortSpan = 64 * 64;
+// Particles per work-group of the sort kernels: each work-group takes a
+// contiguous span of one run (16 particles per thread), so that the
+// particles of one tile, kept together by the previous sort, are counted
+// and placed by about one work-group, with one global atomic per tile.  The
+// spans of all sorting runs are laid end to end (prefix span_off).
+constexpr int kSortSpan = 256 * 16;
+constexpr int kSortPer = kSortSpan / 256;
+
+// Tile keys a work-group counts in LDS: a window centred on the key of the
+// span's first particle.  Particles move a few cells between sorts, so the
+// keys of a span lie within a few tiles of each other (a few rows of tiles
+// in the serpentine order); a key outside the window goes to the global
+// counter directly.
+constexpr int kSortWin = 4096;
+
+__device__ __forceinline__ int sort_window_base(int first_key)
+{
+    return first_key > kSortWin / 2 ? first_key - kSortWin / 2 : 0;
+}
 
 // Clear the tile counters and cursors of the sorting runs (256 per
 // work-group).
@@ -1317,24 +1330,18 @@ __global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__
     }
 }
 
-// Windows of 64 particles a wave loads before it works on them: their
-// loads (and, in the scatter, their counter atomics) are in flight together
-// instead of one round trip per window.
-constexpr int kSortBatch = 4;
-
-// Histogram of tile keys.  Within a span the last run of equal keys of each
-// 64-particle window is kept pending and extended by the next window while
-// the key stays the same; a counter is touched only when a run of keys
-// ends.
+// Histogram of tile keys: LDS counts per span, then one global atomic per
+// key present.  LDS atomics do not share the memory counter that the loads
+// wait on, so a span costs one round trip to memory.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__ runs, int n_runs,
                                                    const unsigned long long *__restrict__ span_off)
 {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
-    const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
+    __shared__ unsigned int h[kSortWin];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
     const unsigned long long nspan = span_off[n_runs];
-    for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
+    for (unsigned long long gs = blockIdx.x; gs < nspan; gs += gridDim.x) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
         const RunDev<T> &R = runs[r];
         const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
@@ -1343,46 +1350,33 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
         const TileMap tm = R.tm;
         const gptr<unsigned int> counts = glb(R.counts);
         const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
-        const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
-        int pend_key = -1;          // wave-uniform pending run of keys
-        unsigned int pend_len = 0;
-        for (unsigned long long bb = s0; bb < s1; bb += 64 * kSortBatch) {
-            uint32_t cw[kSortBatch];
+        const uint32_t ns = (uint32_t)min(n - s0, (unsigned long long)kSortSpan);
+        const gptr<const uint32_t> cs = cell + s0;
+        uint32_t cw[kSortPer];
 #pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long idx = bb + 64 * u + lane;
-                cw[u] = idx < s1 ? cell[idx] : 0u;
-            }
+        for (int u = 0; u < kSortPer; ++u) {
+            const uint32_t k = 256u * u + tid;
+            cw[u] = k < ns ? cs[k] : kDead;
+        }
+        const int base = sort_window_base(tm.key(cs[0]));
+        __syncthreads(); // the window is clear
 #pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long b = bb + 64 * u;
-                if (b >= s1) break;
-                const unsigned long long idx = b + lane;
-                const int key = idx < s1 ? tm.key(cw[u]) : INT_MAX;
-                const int prev = __shfl_up(key, 1);
-                const bool head = lane == 0 || key != prev;
-                const unsigned long long heads = __ballot(head);
-                const unsigned long long after = heads & ~lanemask_le(lane);
-                const int next = after ? __ffsll((long long)after) - 1 : 64;
-                const int nruns = __popcll(heads);
-                const int first_key = __shfl(key, 0);
-                const int first_len = nruns > 1 ? __ffsll((long long)(heads & ~1ull)) - 1 : 64;
-                const int last_lane = 63 - __clzll((long long)heads);
-                const int last_key = __shfl(key, last_lane);
-                const bool extend = pend_key == first_key;
-                if (extend) pend_len += (unsigned int)first_len;
-                if (pend_key >= 0 && (!extend || nruns > 1)) { // the pending run has ended
-                    if (lane == 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
-                }
-                const bool complete = head && lane != last_lane && !(lane == 0 && extend);
-                if (complete && key != INT_MAX) atomic_add(counts + key, (unsigned int)(next - lane));
-                if (!(extend && nruns == 1)) {
-                    pend_key = last_key;
-                    pend_len = (unsigned int)(64 - last_lane);
-                }
+        for (int u = 0; u < kSortPer; ++u) {
+            if (256u * u + tid < ns) {
+                const int key = tm.key(cw[u]);
+                const unsigned int dw = (unsigned int)(key - base);
+                if (dw < (unsigned int)kSortWin) atomicAdd(&h[dw], 1u);
+                else atomic_add(counts + key, 1u);
             }
         }
-        if (lane == 0 && pend_key >= 0 && pend_key != INT_MAX) atomic_add(counts + pend_key, pend_len);
+        __syncthreads();
+        for (int e = tid; e < kSortWin; e += 256) {
+            const unsigned int v = h[e];
+            if (v) {
+                atomic_add(counts + base + e, v);
+                h[e] = 0;
+            }
+        }
     }
 }
 
@@ -1421,90 +1415,105 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
     if (tid == 0) ctr[kLive] = s[1023] - counts[n_keys];
 }
 
-// Scatter into the other buffer: each run of equal keys in a 64-particle
-// window claims its slots with one atomic (kept in particle order within a
-// span).  The keys, the claims and the loads of kSortBatch windows are in
-// flight together.
+// Scatter into the other buffer.  Per span: each particle takes its rank
+// among the span's particles of its key from an LDS atomic; each key present
+// claims its slots with one global atomic on its cursor; the particles are
+// then copied, 4 per thread at a time, to offsets[key] + claim + rank.  The
+// order of equal keys within a span is not kept.  Deleted particles (the
+// last key) are dropped; lanes without a particle write a spare slot past
+// the capacity, so that every lane stores.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restrict__ runs, int n_runs,
                                                       const unsigned long long *__restrict__ span_off)
 {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long wave = (blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x) >> 6;
-    const unsigned long long nwaves = ((unsigned long long)gridDim.x * blockDim.x) >> 6;
+    __shared__ unsigned int h[kSortWin];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
     const unsigned long long nspan = span_off[n_runs];
-    for (unsigned long long gs = wave; gs < nspan; gs += nwaves) {
+    for (unsigned long long gs = blockIdx.x; gs < nspan; gs += gridDim.x) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
         const RunDev<T> &R = runs[r];
         const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
         const unsigned long long n = ctr[kTotal];
         const int cur = (int)ctr[kCur], nxt = cur ^ 1;
-        const gptr<const uint32_t> cell = glb((const uint32_t *)R.cell[cur]);
-        const gptr<uint32_t> cell_o = glb(R.cell[nxt]);
-        const gptr<const uint64_t> id = R.id[cur] ? glb((const uint64_t *)R.id[cur]) : nullptr;
-        const gptr<uint64_t> id_o = glb(R.id[nxt]);
+        const TileMap tm = R.tm;
+        const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
+        const uint32_t ns = (uint32_t)min(n - s0, (unsigned long long)kSortSpan);
+        const gptr<const uint32_t> cs = glb((const uint32_t *)R.cell[cur]) + s0;
         const gptr<const unsigned long long> offsets = glb((const unsigned long long *)R.offsets);
         const gptr<unsigned int> cursor = glb(R.cursor);
+        const uint32_t cap = (uint32_t)R.capacity;
+        uint32_t cw[kSortPer];
+#pragma unroll
+        for (int u = 0; u < kSortPer; ++u) {
+            const uint32_t k = 256u * u + tid;
+            cw[u] = k < ns ? cs[k] : kDead;
+        }
+        const int base = sort_window_base(tm.key(cs[0]));
+        __syncthreads(); // the window is clear
+        // rank within the span among the particles of the same key (in the
+        // window), or the slot itself (outside the window: claimed alone)
+        uint32_t rank[kSortPer];
+#pragma unroll
+        for (int u = 0; u < kSortPer; ++u) {
+            rank[u] = 0;
+            const int key = tm.key(cw[u]);
+            const unsigned int dw = (unsigned int)(key - base);
+            if (256u * u + tid < ns && key != tm.n_keys) {
+                if (dw < (unsigned int)kSortWin) rank[u] = atomicAdd(&h[dw], 1u);
+                else rank[u] = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, 1u));
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kSortWin; e += 256) {
+            const unsigned int v = h[e];
+            if (v) h[e] = (unsigned int)(offsets[base + e] + atomic_add_fetch_old(cursor + base + e, v));
+        }
+        __syncthreads();
+        uint32_t dest[kSortPer];
+#pragma unroll
+        for (int u = 0; u < kSortPer; ++u) {
+            const int key = tm.key(cw[u]);
+            const unsigned int dw = (unsigned int)(key - base);
+            uint32_t d = cap + (uint32_t)(tid & 63); // spare slot
+            if (256u * u + tid < ns && key != tm.n_keys) {
+                const uint32_t t = dw < (unsigned int)kSortWin ? h[dw] + rank[u] : rank[u];
+                if (t < cap) d = t;
+                else atomic_or(glb(R.status), 4); // never write outside the store
+            }
+            dest[u] = d;
+        }
+        __syncthreads();
+        for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
         gptr<const T> src[6];
         gptr<T> dst[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            src[q] = glb((const T *)R.arr[cur][q]);
+            src[q] = glb((const T *)R.arr[cur][q]) + s0;
             dst[q] = glb(R.arr[nxt][q]);
         }
-        const TileMap tm = R.tm;
-        const unsigned long long cap = (unsigned long long)R.capacity;
-        const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
-        const unsigned long long s1 = s0 + kSortSpan < n ? s0 + kSortSpan : n;
-        for (unsigned long long bb = s0; bb < s1; bb += 64 * kSortBatch) {
-            uint32_t cw[kSortBatch];
-            int key[kSortBatch], hl[kSortBatch];
-            unsigned int got[kSortBatch];
+        const gptr<uint32_t> cell_o = glb(R.cell[nxt]);
+        const gptr<const uint64_t> id = R.id[cur] ? glb((const uint64_t *)R.id[cur]) + s0 : nullptr;
+        const gptr<uint64_t> id_o = glb(R.id[nxt]);
 #pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long idx = bb + 64 * u + lane;
-                cw[u] = idx < s1 ? cell[idx] : kDead;
+        for (int g = 0; g < kSortPer; g += 4) {
+            T pay[4][6];
+            uint64_t pid[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t k = 256u * (g + u) + tid;
+                const bool in = k < ns;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) pay[u][q] = in ? src[q][k] : (T)0;
+                pid[u] = (in && id) ? id[k] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long idx = bb + 64 * u + lane;
-                key[u] = idx < s1 ? tm.key(cw[u]) : INT_MAX;
-                const int prev = __shfl_up(key[u], 1);
-                const bool head = lane == 0 || key[u] != prev;
-                const unsigned long long heads = __ballot(head);
-                const unsigned long long after = heads & ~lanemask_le(lane);
-                const int next = after ? __ffsll((long long)after) - 1 : 64;
-                const bool live = key[u] != INT_MAX && key[u] != tm.n_keys;
-                got[u] = 0;
-                if (head && live) got[u] = atomic_add_fetch_old(cursor + key[u], (unsigned int)(next - lane));
-                hl[u] = 63 - __clzll((long long)(heads & lanemask_le(lane)));
-            }
-            // the payloads of all windows are read before any is written
-            T pay[kSortBatch][6];
-            uint64_t pid[kSortBatch];
-            unsigned long long dest[kSortBatch];
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t dd = dest[g + u];
+                cell_o[dd] = cw[g + u];
 #pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long idx = bb + 64 * u + lane;
-                const bool live = key[u] != INT_MAX && key[u] != tm.n_keys;
-                const unsigned int g = __shfl(got[u], hl[u]);
-                dest[u] = live ? offsets[key[u]] + g + (lane - hl[u]) : ~0ull;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) pay[u][q] = live ? src[q][idx] : (T)0;
-                pid[u] = (live && id) ? id[idx] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const unsigned long long d = dest[u];
-                if (d == ~0ull) continue;
-                if (d >= cap) { // never write outside the store
-                    atomic_or(glb(R.status), 4);
-                    continue;
-                }
-                cell_o[d] = cw[u];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) dst[q][d] = pay[u][q];
-                if (id) id_o[d] = pid[u];
+                for (int q = 0; q < 6; ++q) dst[q][dd] = pay[u][q];
+                if (id) id_o[dd] = pid[u];
             }
         }
     }

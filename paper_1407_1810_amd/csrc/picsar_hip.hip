@@ -474,7 +474,7 @@ public:
                 arr_[s][a] = dalloc<T>(cap_ + kMaxChunk);
                 R.arr[s][a] = arr_[s][a];
             }
-            id_[s] = with_ids_ ? dalloc<uint64_t>(std::max<int64_t>(cap_, 1)) : nullptr;
+            id_[s] = with_ids_ ? dalloc<uint64_t>(cap_ + kMaxChunk) : nullptr;
             R.id[s] = id_[s];
         }
         R.capacity = cap_;
