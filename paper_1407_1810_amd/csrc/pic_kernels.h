@@ -1314,6 +1314,27 @@ __device__ __forceinline__ int sort_window_base(int first_key)
     return first_key > kSortWin / 2 ? first_key - kSortWin / 2 : 0;
 }
 
+// Runs of equal keys among the 64 lanes of a wave (particles in lane
+// order, mostly of one tile after the previous sort): whether the lane
+// starts a run, the run's length (valid at its start) and the lane that
+// starts the lane's run.  Counting one atomic per run instead of one per
+// particle keeps the LDS atomics of a wave off one address.
+struct KeyRun {
+    bool head;
+    int len, head_lane;
+};
+__device__ __forceinline__ KeyRun key_run(int key, int lane)
+{
+    const int prev = __shfl_up(key, 1);
+    KeyRun k;
+    k.head = lane == 0 || key != prev;
+    const unsigned long long heads = __ballot(k.head);
+    const unsigned long long after = heads & ~lanemask_le(lane);
+    k.len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
+    k.head_lane = 63 - __clzll((long long)(heads & lanemask_le(lane)));
+    return k;
+}
+
 // Clear the tile counters and cursors of the sorting runs (256 per
 // work-group).
 template <typename T>
@@ -1330,8 +1351,8 @@ __global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__
     }
 }
 
-// Histogram of tile keys: LDS counts per span, then one global atomic per
-// key present.  LDS atomics do not share the memory counter that the loads
+// Histogram of tile keys: LDS counts per span (one atomic per run of equal
+// keys in a wave), then one global atomic per key present.  LDS atomics do not share the memory counter that the loads
 // wait on, so a span costs one round trip to memory.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__ runs, int n_runs,
@@ -1362,11 +1383,12 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
         __syncthreads(); // the window is clear
 #pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
-            if (256u * u + tid < ns) {
-                const int key = tm.key(cw[u]);
+            const int key = 256u * u + tid < ns ? tm.key(cw[u]) : INT_MAX;
+            const KeyRun kr = key_run(key, tid & 63);
+            if (kr.head && key != INT_MAX) {
                 const unsigned int dw = (unsigned int)(key - base);
-                if (dw < (unsigned int)kSortWin) atomicAdd(&h[dw], 1u);
-                else atomic_add(counts + key, 1u);
+                if (dw < (unsigned int)kSortWin) atomicAdd(&h[dw], (unsigned int)kr.len);
+                else atomic_add(counts + key, (unsigned int)kr.len);
             }
         }
         __syncthreads();
@@ -1416,10 +1438,11 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
 }
 
 // Scatter into the other buffer.  Per span: each particle takes its rank
-// among the span's particles of its key from an LDS atomic; each key present
-// claims its slots with one global atomic on its cursor; the particles are
-// then copied, 4 per thread at a time, to offsets[key] + claim + rank.  The
-// order of equal keys within a span is not kept.  Deleted particles (the
+// among the span's particles of its key from an LDS atomic (one per run of
+// equal keys in a wave); each key present claims its slots with one global
+// atomic on its cursor; the particles are then copied, 4 per thread at a
+// time, to offsets[key] + claim + rank.  The order of equal keys is kept
+// within a wave's 64 particles, not across the waves of a span.  Deleted particles (the
 // last key) are dropped; lanes without a particle write a spare slot past
 // the capacity, so that every lane stores.
 template <typename T>
@@ -1452,17 +1475,21 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
         const int base = sort_window_base(tm.key(cs[0]));
         __syncthreads(); // the window is clear
         // rank within the span among the particles of the same key (in the
-        // window), or the slot itself (outside the window: claimed alone)
+        // window), or the slot itself (outside the window: claimed by run);
+        // one atomic per run of equal keys in a wave, ranks follow lane order
         uint32_t rank[kSortPer];
 #pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
-            rank[u] = 0;
-            const int key = tm.key(cw[u]);
-            const unsigned int dw = (unsigned int)(key - base);
-            if (256u * u + tid < ns && key != tm.n_keys) {
-                if (dw < (unsigned int)kSortWin) rank[u] = atomicAdd(&h[dw], 1u);
-                else rank[u] = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, 1u));
+            const int key = 256u * u + tid < ns ? tm.key(cw[u]) : INT_MAX;
+            const bool live = key != INT_MAX && key != tm.n_keys;
+            const KeyRun kr = key_run(key, tid & 63);
+            uint32_t got = 0;
+            if (kr.head && live) {
+                const unsigned int dw = (unsigned int)(key - base);
+                if (dw < (unsigned int)kSortWin) got = atomicAdd(&h[dw], (unsigned int)kr.len);
+                else got = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, (unsigned int)kr.len));
             }
+            rank[u] = (uint32_t)__shfl((int)got, kr.head_lane) + (uint32_t)((tid & 63) - kr.head_lane);
         }
         __syncthreads();
         for (int e = tid; e < kSortWin; e += 256) {

@@ -93,6 +93,32 @@ def test_lds_and_global_paths_and_sort(prec):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
+def test_sort_groups_each_chunk_by_tile(prec):
+    """The first sort puts the generator's shuffled particles in tile order:
+    with exactly 64 particles per cell, tiles of 1 x 32 cells (one row of
+    cells each, so that every tile is full whatever the ghost width) hold
+    2048 particles, and each push chunk (16 x 256 particles) covers two tiles
+    of one row, which the LDS region holds; a sort that left particles out
+    of tile order would send chunks to the global-memory path.  (Once
+    particles move, tiles hold unequal counts and a chunk may reach into a
+    third or fourth tile; some chunks then take the global path by design.)
+    Over three sorted steps no particle is lost or duplicated."""
+    from paper_1407_1810_amd.binding import Sim
+    cfg, P = _small(nr=96, nth=128, pairs_per_cell=32, n_filt=2, bg="dipole")
+    p = cfg["params"]
+    s = Sim(p, precision=prec, capacity=len(P["x"]) + (1 << 20), tile=(1, 32), sort_interval=1, chunk_ppt=16)
+    s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+    s.step(1)
+    assert s.counts()["global_chunks"] == 0
+    s.step(2)
+    c = s.counts()
+    _say(f"{prec}: {c}")
+    ids = s.particles()["id"]
+    assert len(ids) == c["live"] and len(np.unique(ids)) == len(ids)
+    assert c["live"] + c["deleted"] == len(P["x"]) + c["injected"]
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_ten_steps_monopole_rotator_with_injection(prec):
     """Ten steps of a small monopole rotator: spin-up, surface injection
     (same pairs, same Philox positions), deletion, lossy layer."""
