@@ -149,13 +149,15 @@ __device__ inline int run_of(const unsigned long long *__restrict__ off, int n_r
     return lo;
 }
 
-// Field kernels use 64 x 4 work-groups; each thread takes kRowSteps
-// consecutive rows of one column, so a work-group covers 64 columns x
-// kBlockRows rows, the per-work-group run lookup is paid once per
-// kRowSteps cells of a thread, and a thread's loads of neighbouring rows
-// are shared and issued together.
-constexpr int kRowSteps = 8;
-constexpr int kBlockRows = 4 * kRowSteps;
+// Field kernels use 64 x 4 work-groups; each thread takes RS consecutive
+// rows of one column, so a work-group covers 64 columns x 4 RS rows, the
+// per-work-group run lookup is paid once per RS cells of a thread, and a
+// thread's loads of neighbouring rows are shared and issued together.
+// Faraday, Ampere and the lossy layer take 4 rows (more work-groups in
+// flight); the filter takes 8, each of its rows' theta passes serving three
+// outputs.
+constexpr int kFieldRows = 4;
+constexpr int kFilterRows = 8;
 constexpr int kZeroPerThread = 16;
 
 // First (row, column) of thread (threadIdx.x, threadIdx.y) in the local
@@ -163,11 +165,12 @@ constexpr int kZeroPerThread = 16;
 struct Cell2 {
     int i, j;
 };
+template <int RS>
 __device__ inline Cell2 block_cell(int lb, int ncol)
 {
     const int nbx = (ncol + 63) / 64;
     const int by = lb / nbx, bx = lb - by * nbx;
-    return Cell2{by * kBlockRows + kRowSteps * (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
+    return Cell2{by * 4 * RS + RS * (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
 }
 
 template <typename T>
@@ -264,7 +267,7 @@ __device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr
     const gptr<const T> s = glb(m.s), invr = glb(m.invr), icBr = glb(m.icBr), rn = glb(m.r_node),
                         idr2 = glb(m.idr2), dr = glb(m.dr), idth = glb(m.idth);
 #pragma unroll
-    for (int rs = 0; rs < kRowSteps; ++rs) {
+    for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
         if (i > nr) break;
         if (i >= 1 && i < nr && j < nth) {
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ r
 {
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    const Cell2 q = block_cell(blockIdx.x - off[r], R.L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], R.L.nth + 1);
     if (q.j > R.L.nth) return;
     faraday_rows<T>(glb((const T *)R.fld[cER]), glb((const T *)R.fld[cETH]), glb((const T *)R.fld[cEPH]),
                     glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j, hc_frac * R.c);
@@ -312,7 +315,7 @@ __device__ __forceinline__ void ampere_rows(gptr<const T> __restrict__ Br, gptr<
                         ab_half = glb(m.ab_half), rb = glb(m.rb), isb2pi = glb(m.isb2pi), idrb2 = glb(m.idrb2),
                         ab_int = glb(m.ab_int), drb = glb(m.drb), idthb = glb(m.idthb);
 #pragma unroll
-    for (int rs = 0; rs < kRowSteps; ++rs) {
+    for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
         if (i > nr) break;
         if (i < nr) {
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void k_ampere(const RunDev<T> *__restrict__ ru
 {
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    const Cell2 q = block_cell(blockIdx.x - off[r], R.L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], R.L.nth + 1);
     if (q.j > R.L.nth) return;
     ampere_rows<T>(glb((const T *)R.fld[cBR]), glb((const T *)R.fld[cBTH]), glb((const T *)R.fld[cBPH]),
                    glb(R.ffin[0]), glb(R.ffin[1]), glb(R.ffin[2]), glb(R.fld[cER]), glb(R.fld[cETH]),
@@ -357,12 +360,12 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
     const Layout L = R.L;
-    const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], L.nth + 1);
     const int j = q.j;
     if (j > L.nth) return;
     const gptr<const T> ab_int = glb(R.m.ab_int), ab_half = glb(R.m.ab_half);
     const gptr<T> Br = glb(R.fld[cBR]), Bth = glb(R.fld[cBTH]), Bph = glb(R.fld[cBPH]);
-    for (int rs = 0; rs < kRowSteps; ++rs) {
+    for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = L.nr - R.absorb_cells - 1 + q.i + rs;
         if (i > L.nr) return;
         if (i < 0) continue;
@@ -413,7 +416,7 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const Layout L = R.L;
     const int comp = blockIdx.y;
     const int kind = comp == 1 ? 1 : 0;
-    const Cell2 q = block_cell(blockIdx.x - off[r], L.nth + 1);
+    const Cell2 q = block_cell<kFilterRows>(blockIdx.x - off[r], L.nth + 1);
     const int j = q.j;
     const int ncol = kind ? L.nth : L.nth + 1;
     const int last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
@@ -422,15 +425,15 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const gptr<T> dst = glb((pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp]);
     const int i0 = -L.G + q.i;
     if (i0 > last) return;
-    // theta passes of rows i0 - 1 .. i0 + kRowSteps, zero outside [-G, last]
-    T tp[kRowSteps + 2];
+    // theta passes of rows i0 - 1 .. i0 + kFilterRows, zero outside [-G, last]
+    T tp[kFilterRows + 2];
 #pragma unroll
-    for (int rs = 0; rs < kRowSteps + 2; ++rs) {
+    for (int rs = 0; rs < kFilterRows + 2; ++rs) {
         const int i = i0 - 1 + rs;
         tp[rs] = (i >= -L.G && i <= last) ? theta_pass<T>(a, L, i, j, kind) : (T)0;
     }
 #pragma unroll
-    for (int rs = 0; rs < kRowSteps; ++rs) {
+    for (int rs = 0; rs < kFilterRows; ++rs) {
         const int i = i0 + rs;
         if (i > last) break;
         T v = (T)0.5 * tp[rs + 1];

@@ -160,9 +160,9 @@ public:
             const RunDev<T> &R = rd[r];
             const int nbx = (R.L.nth + 1 + 63) / 64;
             const int cnt[kMaps] = {
-                nbx * ((R.L.nr + 1 + kBlockRows - 1) / kBlockRows),
-                nbx * ((R.L.rows() + kBlockRows - 1) / kBlockRows),
-                R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + kBlockRows - 1) / kBlockRows) : 0,
+                nbx * ((R.L.nr + 1 + 4 * kFieldRows - 1) / (4 * kFieldRows)),
+                nbx * ((R.L.rows() + 4 * kFilterRows - 1) / (4 * kFilterRows)),
+                R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + 4 * kFieldRows - 1) / (4 * kFieldRows)) : 0,
                 (int)((R.L.size() + 256 * kZeroPerThread - 1) / (256 * kZeroPerThread)),
                 R.sort_interval > 0 ? (R.tm.n_keys + 1 + 255) / 256 : 0,
             };
