@@ -154,10 +154,8 @@ __device__ inline int run_of(const unsigned long long *__restrict__ off, int n_r
 // per-work-group run lookup is paid once per RS cells of a thread, and a
 // thread's loads of neighbouring rows are shared and issued together.
 // Faraday, Ampere and the lossy layer take 4 rows (more work-groups in
-// flight); the filter takes 8, each of its rows' theta passes serving three
-// outputs.
+// flight).
 constexpr int kFieldRows = 4;
-constexpr int kFilterRows = 8;
 constexpr int kZeroPerThread = 16;
 
 // First (row, column) of thread (threadIdx.x, threadIdx.y) in the local
@@ -402,44 +400,87 @@ __device__ inline T theta_pass(Ptr a, const Layout &L, int i, int j, int kind)
     return v;
 }
 
-// One pass over the three face-charge planes of every run that filters at
-// least pass + 1 times (blockIdx.y = component).  Pass p reads the planes
-// written by pass p - 1: even passes go from the deposit planes to the
-// second set, odd passes back.
-template <typename T>
+// All n_filt passes of the 1-2-1 filter over one face-charge plane of one
+// run in one launch (blockIdx.y = component).  A work-group stages a tile
+// of kFiltTR x kFiltTC entries with H rows and columns of halo (H >= the
+// run's passes), runs the passes in LDS -- each a theta half (the edge and
+// axis rules of the plane's parity) then a radial half, rows outside
+// [-G, last] and columns outside the plane held at zero -- and writes the
+// tile's centre to the second set of planes.  The valid part of the tile
+// shrinks by one row and column per pass, so H passes leave the centre
+// exact.  Each value is formed with the same operations, in the same
+// order, as one pass over the whole plane.
+constexpr int kFiltTR = 16, kFiltTC = 64;
+
+template <typename T, int H>
 __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ runs, int n_runs,
-                                                const int *__restrict__ off, int pass)
+                                                const int *__restrict__ off)
 {
+    constexpr int NR = kFiltTR + 2 * H, NC = kFiltTC + 2 * H, N = NR * NC;
+    __shared__ T sa[N], sb[N], st[N];
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
-    if (pass >= R.n_filt) return;
+    const int passes = R.n_filt;
     const Layout L = R.L;
     const int comp = blockIdx.y;
     const int kind = comp == 1 ? 1 : 0;
-    const Cell2 q = block_cell<kFilterRows>(blockIdx.x - off[r], L.nth + 1);
-    const int j = q.j;
-    const int ncol = kind ? L.nth : L.nth + 1;
-    const int last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
-    if (j >= ncol) return;
-    const gptr<const T> a = glb((const T *)((pass & 1) ? R.ftmp[comp] : R.fld[cFR + comp]));
-    const gptr<T> dst = glb((pass & 1) ? R.fld[cFR + comp] : R.ftmp[comp]);
-    const int i0 = -L.G + q.i;
-    if (i0 > last) return;
-    // theta passes of rows i0 - 1 .. i0 + kFilterRows, zero outside [-G, last]
-    T tp[kFilterRows + 2];
-#pragma unroll
-    for (int rs = 0; rs < kFilterRows + 2; ++rs) {
-        const int i = i0 - 1 + rs;
-        tp[rs] = (i >= -L.G && i <= last) ? theta_pass<T>(a, L, i, j, kind) : (T)0;
+    const int nth = L.nth, ncol = kind ? nth : nth + 1;
+    const int first = -L.G, last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
+    const int lb = blockIdx.x - off[r];
+    const int nbx = (nth + 1 + kFiltTC - 1) / kFiltTC;
+    const int by = lb / nbx, bx = lb - by * nbx;
+    const int i0 = first + by * kFiltTR - H, j0 = bx * kFiltTC - H; // entry (0, 0) of the tile
+    const gptr<const T> src = glb((const T *)R.fld[cFR + comp]);
+    const gptr<T> dst = glb(R.ftmp[comp]);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < N; e += 256) {
+        const int li = e / NC, lj = e - li * NC;
+        const int i = i0 + li, j = j0 + lj;
+        sa[e] = (i >= first && i <= last && j >= 0 && j < ncol) ? src[L.at(i, j)] : (T)0;
     }
-#pragma unroll
-    for (int rs = 0; rs < kFilterRows; ++rs) {
-        const int i = i0 + rs;
-        if (i > last) break;
-        T v = (T)0.5 * tp[rs + 1];
-        v += (T)0.25 * tp[rs];
-        v += (T)0.25 * tp[rs + 2];
-        dst[L.at(i, j)] = v;
+    T *a = sa, *b = sb;
+    for (int p = 0; p < passes; ++p) {
+        __syncthreads();
+        for (int e = tid; e < N; e += 256) { // theta half
+            const int li = e / NC, lj = e - li * NC;
+            const int i = i0 + li, j = j0 + lj;
+            T v = (T)0;
+            if (lj >= 1 && lj < NC - 1 && i >= first && i <= last && j >= 0 && j < ncol) {
+                const T *row = a + e; // row[0] is column j
+                v = (T)0.5 * row[0];
+                if (j > 0) v += (T)0.25 * row[-1];
+                if (j + 1 < ncol) v += (T)0.25 * row[1];
+                if (kind == 0) {
+                    if (j == 1) v += (T)0.25 * row[-1];      // the axis node j = 0, mirrored
+                    if (j == nth - 1) v += (T)0.25 * row[1]; // the axis node j = nth, mirrored
+                } else {
+                    if (j == 0) v -= (T)0.25 * row[0];       // odd parity across the axis
+                    if (j == nth - 1) v -= (T)0.25 * row[0];
+                }
+            }
+            st[e] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < N; e += 256) { // radial half
+            const int li = e / NC, lj = e - li * NC;
+            const int i = i0 + li, j = j0 + lj;
+            T v = (T)0;
+            if (li >= 1 && li < NR - 1 && i >= first && i <= last && j >= 0 && j < ncol) {
+                v = (T)0.5 * st[e];
+                v += (T)0.25 * st[e - NC];
+                v += (T)0.25 * st[e + NC];
+            }
+            b[e] = v;
+        }
+        T *t = a;
+        a = b;
+        b = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < kFiltTR * kFiltTC; e += 256) {
+        const int ci = e / kFiltTC, cj = e - ci * kFiltTC;
+        const int i = i0 + H + ci, j = j0 + H + cj;
+        if (i <= last && j < ncol) dst[L.at(i, j)] = a[(H + ci) * NC + H + cj];
     }
 }
 

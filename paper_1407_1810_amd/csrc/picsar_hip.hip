@@ -161,7 +161,7 @@ public:
             const int nbx = (R.L.nth + 1 + 63) / 64;
             const int cnt[kMaps] = {
                 nbx * ((R.L.nr + 1 + 4 * kFieldRows - 1) / (4 * kFieldRows)),
-                nbx * ((R.L.rows() + 4 * kFilterRows - 1) / (4 * kFilterRows)),
+                R.n_filt > 0 ? ((R.L.nth + 1 + kFiltTC - 1) / kFiltTC) * ((R.L.rows() + kFiltTR - 1) / kFiltTR) : 0,
                 R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + 4 * kFieldRows - 1) / (4 * kFieldRows)) : 0,
                 (int)((R.L.size() + 256 * kZeroPerThread - 1) / (256 * kZeroPerThread)),
                 R.sort_interval > 0 ? (R.tm.n_keys + 1 + 255) / 256 : 0,
@@ -301,8 +301,11 @@ private:
         k_faraday<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid), (T)0.5);
         HIPCHK(hipGetLastError());
         mark(t, s, kStFilter, true);
-        for (int pss = 0; pss < max_filt_; ++pss) {
-            k_filter<T><<<dim3(tot_[kMapFilter], 3), blk2, 0, s>>>(runs_, n_, map(kMapFilter), pss);
+        if (tot_[kMapFilter] > 0) {
+            const dim3 fg(tot_[kMapFilter], 3);
+            if (max_filt_ <= 2) k_filter<T, 2><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
+            else if (max_filt_ <= 4) k_filter<T, 4><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
+            else k_filter<T, 8><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
             HIPCHK(hipGetLastError());
         }
         mark(t, s, kStFilter, false);
@@ -443,8 +446,8 @@ public:
             ftmp_[c] = dalloc<T>(fsz);
             fill(ftmp_[c], fsz, (T)0);
             R.ftmp[c] = ftmp_[c];
-            // even pass counts end in the deposit planes, odd ones in the second set
-            R.ffin[c] = (gd.n_filt & 1) ? ftmp_[c] : fld_[6 + c];
+            // the filter writes the second set of planes
+            R.ffin[c] = gd.n_filt > 0 ? ftmp_[c] : fld_[6 + c];
         }
         build_tables();
         R.m = m_;
