@@ -767,31 +767,26 @@ __device__ __forceinline__ void vb_piece(const D &d, typename D::Off e, T xa, T 
 template <typename T, typename D>
 __device__ inline void vb_deposit(const D &d, int i, int j, int nth, T x0, T y0, T x1, T y1, T Q, T dphi)
 {
-    int cx = 0, cy = 0;
-    T X = 0, Y = 0;
-    if (x1 >= (T)1) { cx = 1; X = (T)1; } else if (x1 < (T)0) { cx = -1; X = (T)0; }
-    if (y1 >= (T)1 && j < nth - 1) { cy = 1; Y = (T)1; } else if (y1 < (T)0) { cy = -1; Y = (T)0; }
+    const int cx = x1 >= (T)1 ? 1 : (x1 < (T)0 ? -1 : 0);
+    const int cy = (y1 >= (T)1 && j < nth - 1) ? 1 : (y1 < (T)0 ? -1 : 0);
+    const T X = cx > 0 ? (T)1 : (T)0, Y = cy > 0 ? (T)1 : (T)0;
+    // path parameters of the crossings (2: none) and the other coordinate
+    // there; formed on every lane and selected, so that lanes with different
+    // crossings share one instruction stream
+    const T dx = x1 - x0, dy = y1 - y0;
+    const T tx = cx ? FM<T>::div(X - x0, dx) : (T)2, ty = cy ? FM<T>::div(Y - y0, dy) : (T)2;
+    const T yx = y0 + tx * dy, xy = x0 + ty * dx;
+    const bool both = cx != 0 && cy != 0, xf = tx < ty, yf = ty < tx;
     // split points s1, s2 (n of them) between the start and the end; the
     // middle piece lies in cell (i + a, j + b)
-    int n = 0, a = cx, b = cy;
-    T s1x = x1, s1y = y1, s2x = x1, s2y = y1;
-    if (cx && cy) {
-        const T tx = FM<T>::div(X - x0, x1 - x0), ty = FM<T>::div(Y - y0, y1 - y0);
-        const T yx = y0 + tx * (y1 - y0), xy = x0 + ty * (x1 - x0);
-        if (tx < ty) {
-            s1x = X; s1y = yx; s2x = xy; s2y = Y; b = 0; n = 2;
-        } else if (ty < tx) {
-            s1x = xy; s1y = Y; s2x = X; s2y = yx; a = 0; n = 2;
-        } else {
-            s1x = X; s1y = Y; n = 1;
-        }
-    } else if (cx) {
-        const T tx = FM<T>::div(X - x0, x1 - x0);
-        s1x = X; s1y = y0 + tx * (y1 - y0); n = 1;
-    } else if (cy) {
-        const T ty = FM<T>::div(Y - y0, y1 - y0);
-        s1x = x0 + ty * (x1 - x0); s1y = Y; n = 1;
-    }
+    const bool two = both && (xf || yf);
+    const int n = two ? 2 : ((cx != 0 || cy != 0) ? 1 : 0);
+    T s1x = x1, s1y = y1;
+    if (xf) { s1x = X; s1y = yx; }
+    else if (yf) { s1x = xy; s1y = Y; }
+    else if (both) { s1x = X; s1y = Y; } // both faces at once: the corner
+    const T s2x = two ? (xf ? xy : X) : x1, s2y = two ? (xf ? Y : yx) : y1;
+    const int a = two && !xf ? 0 : cx, b = two && xf ? 0 : cy;
     const typename D::Off e = d.at(i, j);
     vb_piece(d, e, x0, y0, s1x, s1y, (T)0, (T)0, Q);
     if (n >= 1) vb_piece(d, e + d.step(a, b), s1x, s1y, s2x, s2y, (T)a, (T)b, Q);
@@ -968,12 +963,11 @@ __device__ inline POut<T> push_particle(const PushArgs<T> &p, const V &view, con
     vb_deposit(dep, i, j, nth, fx, fy, X1, Y1, w * dep.unit(), FM<T>::atan2(sph, cph));
     const T k1 = zs * isq, s1 = Rn * isq;
     const T ux = cph * uc[0] + sph * uc[1], uy = -sph * uc[0] + cph * uc[1], uz = uc[2];
-    int ni = i, nj = j;
-    T nx = X1, ny = Y1;
-    if (nx >= (T)1) { ++ni; nx -= (T)1; }
-    else if (nx < (T)0) { --ni; nx += (T)1; if (nx >= (T)1) nx = below_one<T>(); }
-    if (ny >= (T)1) { ++nj; ny -= (T)1; }
-    else if (ny < (T)0) { --nj; ny += (T)1; if (ny >= (T)1) ny = below_one<T>(); }
+    // new cell: X1, Y1 lie in (-1, 2); an offset below zero rounds up to at
+    // most the largest value below one
+    const T fxl = floor(X1), fyl = floor(Y1);
+    int ni = i + (int)fxl, nj = j + (int)fyl;
+    T nx = fmin(X1 - fxl, below_one<T>()), ny = fmin(Y1 - fyl, below_one<T>());
     if (nj > nth - 1) { nj = nth - 1; ny = (T)1; }      // y' = nth belongs to the last cell
     POut<T> o;
     o.fx = nx;
