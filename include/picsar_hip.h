@@ -187,6 +187,26 @@ pic_status pic_set_sort(pic_ctx *ctx, int32_t tile_r, int32_t tile_th, int32_t s
 pic_status pic_autotune(pic_ctx *ctx, const int32_t *cand, int32_t n_cand, int32_t steps, int32_t *best,
                         double *best_ns);
 
+/* Checkpoint and resume, for runs longer than one process (the paper's
+ * rotator runs last tens of thousands of steps).  pic_save writes the whole
+ * state of an initialised context to the file `path` (created or
+ * truncated): its grid and physics descriptors (with the sort tile,
+ * interval and chunk size in use), step index and counters, the
+ * fixed-point deposit scale, the injection carry, the nine field planes and
+ * the filtered face charges, and every particle slot as stored -- int32
+ * cell, offsets, momenta and weight in the context's precision, ids -- so
+ * that nothing passes through an FP64 conversion.  pic_load restores such
+ * a file into a context made by pic_create and not initialised, which then
+ * continues the run from the same bits.  The file is this library's own
+ * format (a versioned header, then the arrays, host byte order).
+ * PIC_ESTATE for pic_save before pic_init or pic_load after it; PIC_EINVAL
+ * for a null path, a file that cannot be opened, written or read whole, a
+ * file that is not a checkpoint of this version, or one whose descriptors,
+ * counters, cells or offsets are out of range; PIC_ECAPACITY if its
+ * particles exceed its capacity; PIC_EDEVICE for HIP errors. */
+pic_status pic_save(pic_ctx *ctx, const char *path);
+pic_status pic_load(pic_ctx *ctx, const char *path);
+
 /* Message of the last failed call on ctx (empty if none). */
 const char *pic_last_error(const pic_ctx *ctx);
 

@@ -31,7 +31,7 @@ STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "
 
 EXPORTED = ["pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
             "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
-            "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_last_error", "pic_destroy",
+            "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_save", "pic_load", "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing",
             "pic_batch_stage_ms", "pic_batch_last_error", "pic_batch_destroy"]
 
@@ -82,6 +82,8 @@ def lib():
         L.pic_set_timing.argtypes = [vp, i32]
         L.pic_set_sort.argtypes = [vp, i32, i32, i32]
         L.pic_autotune.argtypes = [vp, P(i32), i32, i32, P(i32), P(d)]
+        L.pic_save.argtypes = [vp, C.c_char_p]
+        L.pic_load.argtypes = [vp, C.c_char_p]
         L.pic_last_error.argtypes = [vp]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [vp]
@@ -152,6 +154,31 @@ class Sim:
         self.nr, self.nth = g.nr, g.nth
         self.precision = precision
         self._check(L.pic_init(self._h, C.byref(g), C.byref(ph)))
+
+    @classmethod
+    def load(cls, path, device: int = 0, stream=None):
+        """A simulation restored from a checkpoint written by save(): the
+        same grid, physics, sort settings and state, continuing the run."""
+        self = cls.__new__(cls)
+        L = lib()
+        self._h = C.c_void_p()
+        rc = L.pic_create(C.byref(self._h), int(device), stream)
+        if rc != 0:
+            raise PicError(rc, "pic_create failed (no HIP device?)")
+        try:
+            self._check(L.pic_load(self._h, os.fsencode(os.fspath(path))))
+            rows, cols, row0 = C.c_int32(), C.c_int32(), C.c_int32()
+            self._check(L.pic_field_shape(self._h, COMPS.index("Eph"), C.byref(rows), C.byref(cols), C.byref(row0)))
+        except Exception:
+            self.close()
+            raise
+        self.grid = self.phys = self.precision = None
+        self.nr, self.nth = rows.value - 1, cols.value - 1
+        return self
+
+    def save(self, path):
+        """Checkpoint the whole state to `path` (see pic_save)."""
+        self._check(lib().pic_save(self._h, os.fsencode(os.fspath(path))))
 
     def _check(self, rc):
         if rc != 0:

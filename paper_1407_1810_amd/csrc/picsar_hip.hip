@@ -352,6 +352,38 @@ struct Geometry {
     }
 };
 
+// Checkpoint file: this header, then the twelve field planes (E, B, the
+// deposit planes, the filtered face charges; the padded device layout of
+// field_elems entries each, in the context's precision), the injection carry
+// (nth + 1 doubles), and the particle slots: cell indices (uint32), the six
+// particle arrays (offsets, momenta, weight; the context's precision) and,
+// with ids, the uint64 ids.
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t real_bytes;
+    pic_grid_desc grid;       // with the sort tile, interval and chunk size in use
+    pic_phys_desc phys;
+    uint64_t counters[kNumCounters];
+    double qmax;              // largest |w| held: the fixed-point deposit scale
+    uint64_t slots;           // particle slots written (live and deleted)
+    uint64_t field_elems;     // entries per field plane
+    uint32_t n_planes;
+    uint32_t with_ids;
+};
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'S', 'A', 'R', 'C', 'K'};
+constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptPlanes = 12;
+
+inline void ck_write(FILE *f, const void *p, size_t bytes)
+{
+    if (bytes && std::fwrite(p, 1, bytes, f) != bytes) throw StatusError{PIC_EINVAL, "checkpoint write failed"};
+}
+inline void ck_read(FILE *f, void *p, size_t bytes)
+{
+    if (bytes && std::fread(p, 1, bytes, f) != bytes) throw StatusError{PIC_EINVAL, "checkpoint file truncated"};
+}
+
 class Engine {
 public:
     virtual ~Engine() {}
@@ -374,6 +406,10 @@ public:
     virtual double timed_steps(int n, double *psteps) = 0;
     // device status bits of the run (cleared on read)
     virtual int take_status() = 0;
+    // checkpoint: the whole state to / from an open file (the header of a
+    // restore has been read and checked by the caller)
+    virtual void save(FILE *f) = 0;
+    virtual void restore(FILE *f, const struct CkptHeader &h) = 0;
 
     pic_grid_desc gd{};
     pic_phys_desc ph{};
@@ -742,6 +778,119 @@ public:
         out[2] = rd_.sort_interval;
     }
 
+    // device array -> file, through a host buffer of at most 16M entries
+    template <typename U>
+    void dump(FILE *f, const U *d, size_t n)
+    {
+        std::vector<U> h(std::min<size_t>(n, (size_t)1 << 24));
+        for (size_t o = 0; o < n; o += h.size()) {
+            const size_t m = std::min(h.size(), n - o);
+            HIPCHK(hipMemcpyAsync(h.data(), d + o, sizeof(U) * m, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            ck_write(f, h.data(), sizeof(U) * m);
+        }
+    }
+    // file -> device array; `check(values, count, first index)` sees every
+    // chunk on the host before it is uploaded
+    template <typename U, typename F>
+    void undump(FILE *f, U *d, size_t n, F check)
+    {
+        std::vector<U> h(std::min<size_t>(n, (size_t)1 << 24));
+        for (size_t o = 0; o < n; o += h.size()) {
+            const size_t m = std::min(h.size(), n - o);
+            ck_read(f, h.data(), sizeof(U) * m);
+            check(h.data(), m, o);
+            HIPCHK(hipMemcpyAsync(d + o, h.data(), sizeof(U) * m, hipMemcpyHostToDevice, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+        }
+    }
+    template <typename U>
+    void undump(FILE *f, U *d, size_t n)
+    {
+        undump(f, d, n, [](const U *, size_t, size_t) {});
+    }
+
+    void save(FILE *f) override
+    {
+        HIPCHK(hipStreamSynchronize(stream));
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        CkptHeader h{};
+        std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+        h.version = kCkptVersion;
+        h.real_bytes = sizeof(T);
+        h.grid = gd;
+        h.grid.tile_r = rd_.tm.tile_r;
+        h.grid.tile_th = rd_.tm.tile_th;
+        h.grid.sort_interval = rd_.sort_interval;
+        h.grid.chunk_ppt = ppt_;
+        h.phys = ph;
+        for (int k = 0; k < kNumCounters; ++k) h.counters[k] = c[k];
+        h.qmax = qmax_;
+        h.slots = c[kTotal];
+        h.field_elems = L.size();
+        h.n_planes = kCkptPlanes;
+        h.with_ids = with_ids_ ? 1u : 0u;
+        ck_write(f, &h, sizeof h);
+        for (int q = 0; q < 9; ++q) dump(f, fld_[q], L.size());
+        for (int q = 0; q < 3; ++q) dump(f, ftmp_[q], L.size());
+        dump(f, carry_, (size_t)gd.nth + 1);
+        const int cur = (int)c[kCur];
+        dump(f, cell_[cur], h.slots);
+        for (int a = 0; a < 6; ++a) dump(f, arr_[cur][a], h.slots);
+        if (with_ids_) dump(f, id_[cur], h.slots);
+    }
+
+    // state of a fresh context (just initialised from the header's
+    // descriptors) from the rest of the file
+    void restore(FILE *f, const CkptHeader &h) override
+    {
+        if (h.field_elems != L.size() || h.n_planes != kCkptPlanes || h.real_bytes != sizeof(T) ||
+            h.with_ids != (with_ids_ ? 1u : 0u))
+            throw StatusError{PIC_EINVAL, "checkpoint does not match its own descriptors"};
+        if ((int64_t)h.slots > cap_) throw StatusError{PIC_ECAPACITY, "checkpoint holds more particles than the capacity"};
+        if (h.counters[kTotal] != h.slots || h.counters[kDeadSinceSort] > h.slots || h.counters[kLive] > h.slots ||
+            h.counters[kCur] > 1 || !(h.qmax >= 0.0))
+            throw StatusError{PIC_EINVAL, "checkpoint counters are inconsistent"};
+        for (int q = 0; q < 9; ++q) undump(f, fld_[q], L.size());
+        for (int q = 0; q < 3; ++q) undump(f, ftmp_[q], L.size());
+        undump(f, carry_, (size_t)gd.nth + 1);
+        // the kernels index fields and LDS by these: every cell must lie where
+        // a particle may be, every offset inside its cell
+        const int lim = gd.n_filt + 1, nr = gd.nr, nth = gd.nth;
+        std::vector<uint8_t> last_row; // an offset of 1 in y belongs to the last row (or a deleted slot)
+        last_row.reserve(h.slots);
+        undump(f, cell_[0], h.slots, [&](const uint32_t *c, size_t m, size_t) {
+            for (size_t q = 0; q < m; ++q) {
+                const bool ok = c[q] == kDead || (cell_i(c[q]) >= -lim && cell_i(c[q]) <= nr + lim &&
+                                                  cell_j(c[q]) >= 0 && cell_j(c[q]) <= nth - 1);
+                if (!ok) throw StatusError{PIC_EINVAL, "checkpoint cell index out of range"};
+                last_row.push_back(c[q] == kDead || cell_j(c[q]) == nth - 1);
+            }
+        });
+        undump(f, arr_[0][0], h.slots, [&](const T *v, size_t m, size_t) {
+            for (size_t q = 0; q < m; ++q)
+                if (!(v[q] >= (T)0 && v[q] < (T)1)) throw StatusError{PIC_EINVAL, "checkpoint offset out of range"};
+        });
+        undump(f, arr_[0][1], h.slots, [&](const T *v, size_t m, size_t o) {
+            for (size_t q = 0; q < m; ++q)
+                if (!(v[q] >= (T)0 && (v[q] < (T)1 || (v[q] == (T)1 && last_row[o + q]))))
+                    throw StatusError{PIC_EINVAL, "checkpoint offset out of range"};
+        });
+        for (int a = 2; a < 6; ++a) undump(f, arr_[0][a], h.slots);
+        if (with_ids_) undump(f, id_[0], h.slots);
+        unsigned long long c[kNumCounters];
+        for (int k = 0; k < kNumCounters; ++k) c[k] = h.counters[k];
+        c[kCur] = 0;
+        HIPCHK(hipMemcpyAsync(ctr_, c, sizeof c, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        qmax_ = h.qmax;
+        if (set_dep_scale()) {
+            plan_.upload({rd_}, stream);
+            ++version;
+        }
+    }
+
     // n steps replayed from the graph; device time in ms between HIP events
     // around them, and the particle-steps they advanced
     double timed_steps(int n, double *psteps) override
@@ -1094,6 +1243,21 @@ Batch *make_batch(pic_ctx *const *runs, int n, hipStream_t s)
 
 } // namespace
 
+// Descriptors a context can be initialised with (pic_init and pic_load).
+void validate(const pic_grid_desc &g, const pic_phys_desc &ph)
+{
+    if (g.nr < 2 || g.nth < 4 || g.nth > 8191 || g.nr > 16000 || !(g.r_in > 0) || !(g.r_out > g.r_in) ||
+        !(g.c > 0) || g.n_filt < 0 || g.n_filt > 8 || g.absorb_cells < 0 || g.absorb_cells > g.nr ||
+        g.particle_capacity < 0 || g.particle_capacity > INT32_MAX ||
+        (g.precision != PIC_FP64 && g.precision != PIC_FP32) ||
+        (g.mover != PIC_VAY && g.mover != PIC_BORIS) || (g.r_kind != PIC_R_LOG && g.r_kind != PIC_R_LIN) ||
+        (g.th_kind != PIC_TH_EQAREA && g.th_kind != PIC_TH_LIN) || g.tile_r < 0 || g.tile_th < 0 ||
+        !(g.chunk_ppt == 0 || g.chunk_ppt == 4 || g.chunk_ppt == 8 || g.chunk_ppt == 16))
+        throw StatusError{PIC_EINVAL, "invalid grid descriptor"};
+    if (ph.bg_kind < PIC_BG_NONE || ph.bg_kind > PIC_BG_DIPOLE_COROT || !(ph.q_inj > 0 || !ph.inject))
+        throw StatusError{PIC_EINVAL, "invalid physics descriptor"};
+}
+
 extern "C" {
 
 pic_status pic_create(pic_ctx **out, int device, void *hip_stream)
@@ -1127,17 +1291,8 @@ pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc
     return guarded(ctx, [&] {
         if (ctx->eng) throw StatusError{PIC_ESTATE, "pic_init called twice"};
         if (!grid || !phys) throw StatusError{PIC_EINVAL, "null descriptor"};
+        validate(*grid, *phys);
         const pic_grid_desc &g = *grid;
-        if (g.nr < 2 || g.nth < 4 || g.nth > 8191 || g.nr > 16000 || !(g.r_in > 0) || !(g.r_out > g.r_in) ||
-            !(g.c > 0) || g.n_filt < 0 || g.n_filt > 8 || g.absorb_cells < 0 || g.absorb_cells > g.nr ||
-            g.particle_capacity < 0 || g.particle_capacity > INT32_MAX ||
-            (g.precision != PIC_FP64 && g.precision != PIC_FP32) ||
-            (g.mover != PIC_VAY && g.mover != PIC_BORIS) || (g.r_kind != PIC_R_LOG && g.r_kind != PIC_R_LIN) ||
-            (g.th_kind != PIC_TH_EQAREA && g.th_kind != PIC_TH_LIN) || g.tile_r < 0 || g.tile_th < 0 ||
-            !(g.chunk_ppt == 0 || g.chunk_ppt == 4 || g.chunk_ppt == 8 || g.chunk_ppt == 16))
-            throw StatusError{PIC_EINVAL, "invalid grid descriptor"};
-        if (phys->bg_kind < PIC_BG_NONE || phys->bg_kind > PIC_BG_DIPOLE_COROT || !(phys->q_inj > 0 || !phys->inject))
-            throw StatusError{PIC_EINVAL, "invalid physics descriptor"};
         Engine *e = g.precision == PIC_FP32 ? (Engine *)new EngineT<float>() : (Engine *)new EngineT<double>();
         e->gd = g;
         e->ph = *phys;
@@ -1318,6 +1473,56 @@ pic_status pic_autotune(pic_ctx *ctx, const int32_t *cand, int32_t n_cand, int32
         best[1] = c[1];
         best[2] = c[2];
         if (best_ns) *best_ns = bcost;
+    });
+}
+
+pic_status pic_save(pic_ctx *ctx, const char *path)
+{
+    return guarded(ctx, [&] {
+        need_engine(ctx);
+        if (!path) throw StatusError{PIC_EINVAL, "null path"};
+        FILE *f = std::fopen(path, "wb");
+        if (!f) throw StatusError{PIC_EINVAL, std::string("cannot create ") + path};
+        try {
+            ctx->eng->save(f);
+        } catch (...) {
+            std::fclose(f);
+            throw;
+        }
+        if (std::fclose(f) != 0) throw StatusError{PIC_EINVAL, std::string("cannot write ") + path};
+    });
+}
+
+pic_status pic_load(pic_ctx *ctx, const char *path)
+{
+    return guarded(ctx, [&] {
+        if (ctx->eng) throw StatusError{PIC_ESTATE, "pic_load needs a context without pic_init"};
+        if (!path) throw StatusError{PIC_EINVAL, "null path"};
+        FILE *f = std::fopen(path, "rb");
+        if (!f) throw StatusError{PIC_EINVAL, std::string("cannot open ") + path};
+        Engine *e = nullptr;
+        try {
+            CkptHeader h{};
+            ck_read(f, &h, sizeof h);
+            if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0 || h.version != kCkptVersion)
+                throw StatusError{PIC_EINVAL, "not a checkpoint of this library version"};
+            const bool fp32 = h.grid.precision == PIC_FP32;
+            if ((fp32 ? 4u : 8u) != h.real_bytes || (!fp32 && h.grid.precision != PIC_FP64))
+                throw StatusError{PIC_EINVAL, "checkpoint precision is inconsistent"};
+            validate(h.grid, h.phys);
+            e = fp32 ? (Engine *)new EngineT<float>() : (Engine *)new EngineT<double>();
+            e->gd = h.grid;
+            e->ph = h.phys;
+            e->stream = ctx->stream;
+            e->init();
+            e->restore(f, h);
+        } catch (...) {
+            std::fclose(f);
+            delete e;
+            throw;
+        }
+        std::fclose(f);
+        ctx->eng = e;
     });
 }
 
