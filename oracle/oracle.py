@@ -80,6 +80,7 @@ def lib():
         L.ora_get_carry.argtypes = [C.c_void_p, P(d)]
         L.ora_set_carry.argtypes = [C.c_void_p, P(d)]
         L.ora_gauss.argtypes = [C.c_void_p, P(d), P(d)]
+        L.ora_poynting.argtypes = [C.c_void_p, P(d)]
         L.ora_geometry.argtypes = [C.c_void_p, C.c_int, P(d)]
         L.ora_push_cartesian.argtypes = [C.c_int, P(d), P(d), P(d), d, P(d)]
         L.ora_background.argtypes = [C.c_void_p, d, d, d, P(d), P(d)]
@@ -241,6 +242,12 @@ class Oracle:
         Q = np.zeros_like(G)
         self._check(lib().ora_gauss(self._h, _dp(G), _dp(Q)))
         return G, Q
+
+    def luminosity(self):
+        """Poynting luminosity through the sphere of each radial half-node."""
+        out = np.zeros(self.nr)
+        self._check(lib().ora_poynting(self._h, _dp(out)))
+        return out
 
     def geometry(self, which):
         sizes = {0: self.nr + 1, 1: self.nr, 2: self.nth + 1, 3: self.nth + 1, 4: self.nth + 1,

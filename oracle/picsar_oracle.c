@@ -1007,6 +1007,37 @@ int ora_gauss(const ora_sim *s, double *G, double *Q)
     return ORA_OK;
 }
 
+/* Spindown luminosity (Sec. 5.4, Fig. 8d: the Poynting flux integrated
+ * over a sphere).  reading: through the sphere of each radial half-node
+ * rbar_i = r(i + 1/2), i = 0..nr-1, with the total fields -- the plasma
+ * field plus the analytic initial field at the current time -- at the cell
+ * centres (i + 1/2, j + 1/2): E_theta the mean of its two radial nodes,
+ * E_phi of its four corners, B_theta of its two meridional nodes, B_phi at
+ * its own point.  Each cell contributes c (E_theta B_phi - E_phi B_theta)
+ * times its face on the sphere, 2 pi rbar^2 (cos theta_j - cos theta_j+1)
+ * (Lorentz-Heaviside units: S = c E x B). */
+int ora_poynting(const ora_sim *s, double *L)
+{
+    const int nr = s->p.nr, nth = s->p.nth;
+    const double t = (double)s->step;
+    for (int i = 0; i < nr; ++i) {
+        const double x = i + 0.5, r = f_r(s, x);
+        double sum = 0.0;
+        for (int j = 0; j < nth; ++j) {
+            const double y = j + 0.5;
+            double Eb[3], Bb[3];
+            background_at(s, x, r, cos_th(s, y), sin_th(s, y), t, Eb, Bb);
+            const double eth = 0.5 * (ETH(i, j) + ETH(i + 1, j)) + Eb[1];
+            const double eph = 0.25 * (EPH(i, j) + EPH(i + 1, j) + EPH(i, j + 1) + EPH(i + 1, j + 1)) + Eb[2];
+            const double bth = 0.5 * (BTH(i, j) + BTH(i, j + 1)) + Bb[1];
+            const double bph = BPH(i, j) + Bb[2];
+            sum += (eth * bph - eph * bth) * 2.0 * PI * r * r * (cos_th(s, j) - cos_th(s, j + 1));
+        }
+        L[i] = s->p.c * sum;
+    }
+    return ORA_OK;
+}
+
 /* geometry tables for the pin tests:
  * 0: r_i (nr+1)   1: rbar_i (nr)   2: cos theta_j (nth+1)   3: theta_j (nth+1)
  * 4: dual face area of node j on the inner conductor, dA_tp(r_in, ...) (nth+1)

@@ -96,6 +96,9 @@ int ora_set_carry(ora_sim *s, const double *in);
  * G = closed-surface flux of E through the dual cell, Q = filtered node
  * charge of the particles.  Rows i = 0 and i = nr are left at zero. */
 int ora_gauss(const ora_sim *s, double *G, double *Q);
+/* Poynting luminosity through the sphere of each radial half-node
+ * (nr values), total fields at the current time (Sec. 5.4). */
+int ora_poynting(const ora_sim *s, double *L);
 
 /* unit-level entry points used by the pin tests */
 int ora_geometry(const ora_sim *s, int which, double *out);

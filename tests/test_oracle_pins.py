@@ -127,6 +127,46 @@ def test_monopole_fields_closed_form():
 
 
 # --------------------------------------------------------------------------
+# Spindown luminosity diagnostic (Sec. 5.4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r_kind,th_kind", [("log", "eqarea"), ("lin", "lin")])
+def test_luminosity_of_michels_field(r_kind, th_kind):
+    """Michel's force-free monopole outside the star, B_phi = E_theta =
+    -B0 r0^2 sin(theta) / (r R_l), written onto the staggered grid as the
+    plasma field (no rotating background, so the only E is Michel's): the
+    Poynting flux through every sphere is L0 = (8 pi / 3) c (B0 r0^2 / R_l)^2
+    (Lorentz-Heaviside), up to the grid's second-order quadrature error."""
+    p = _grid(48, 192, 4.0, r_kind=r_kind, th_kind=th_kind, bg_kind="monopole", B0=1.5, omega=0.0)
+    o = O.Oracle(p)
+    r0, B0, c = p["r_in"], p["B0"], p["c"]
+    Rl = 3.0 * r0
+    rn, rb = o.geometry(0), o.geometry(1)
+    th = o.geometry(3)
+    tb = 0.5 * (th[:-1] + th[1:]) if th_kind == "lin" else np.arccos(1.0 - 2.0 * (np.arange(192) + 0.5) / 192)
+    eth = -B0 * r0 ** 2 * np.sin(tb)[None, :] / (rn[:, None] * Rl)  # (i, j + 1/2)
+    bph = -B0 * r0 ** 2 * np.sin(tb)[None, :] / (rb[:, None] * Rl)  # (i + 1/2, j + 1/2)
+    o.set_field("Eth", eth)
+    o.set_field("Bph", bph)
+    L = o.luminosity()
+    L0 = 8.0 * math.pi / 3.0 * c * (B0 * r0 ** 2 / Rl) ** 2
+    assert L.shape == (48,)
+    assert np.abs(L / L0 - 1.0).max() < 1e-3
+    o.set_field("Bph", -bph)  # the flux reverses with B_phi
+    assert np.allclose(o.luminosity(), -L, rtol=0, atol=1e-12 * L0)
+
+
+@pytest.mark.parametrize("bg", ["monopole", "dipole"])
+def test_luminosity_of_the_background_alone_is_zero(bg):
+    """The analytic initial field of a spinning star is poloidal B with
+    meridional E: no radial Poynting flux."""
+    p = _grid(24, 32, 6.0, bg_kind=bg, B0=1.0, omega=0.05)
+    o = O.Oracle(p)
+    o.set_step_index(37)
+    assert np.array_equal(o.luminosity(), np.zeros(24))
+
+
+# --------------------------------------------------------------------------
 # Movers (Sec. 3.3, Sec. 4.3)
 # --------------------------------------------------------------------------
 
