@@ -159,8 +159,17 @@ pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, dou
  *                  the steps of the last pic_step call (out[0..8] = sort,
  *                  first faraday, push, filter, ampere, absorb, inject,
  *                  zeroing, whole step), from HIP events recorded on the
- *                  context stream -- only when timing is on */
-enum { PIC_MOM_COUNTS = 0, PIC_MOM_GAUSS = 1, PIC_MOM_CARRY = 2, PIC_MOM_STAGE_MS = 3 };
+ *                  context stream -- only when timing is on
+ *  PIC_MOM_POYNTING: spindown luminosity (Sec. 5.4), out[i] for
+ *                  i = 0..nr-1 = the Poynting flux c (E x B)_r, in FP64,
+ *                  of the total field (plasma field plus the analytic
+ *                  initial field at the current step) through the sphere
+ *                  of radial half-node i + 1/2: per meridional cell
+ *                  E_theta averaged over its two radial nodes, E_phi over
+ *                  its four corners, B_theta over its two meridional
+ *                  nodes, B_phi at its own point, times the cell's face
+ *                  2 pi r(i+1/2)^2 (cos theta_j - cos theta_j+1) (nr) */
+enum { PIC_MOM_COUNTS = 0, PIC_MOM_GAUSS = 1, PIC_MOM_CARRY = 2, PIC_MOM_STAGE_MS = 3, PIC_MOM_POYNTING = 4 };
 pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap);
 
 /* Set the step index (time t = index * dt) and the injection carry, so a

@@ -20,7 +20,7 @@ MOVER = {"vay": 0, "boris": 1}
 BG_KIND = {"none": 0, "uniform_bz": 1, "monopole": 2, "dipole": 3, "dipole_corot": 4}
 COMPS = ["Er", "Eth", "Eph", "Br", "Bth", "Bph", "Fr", "Fth", "Fph"]
 FLAG_IDS = 1
-MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS = 0, 1, 2, 3
+MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS, MOM_POYNTING = 0, 1, 2, 3, 4
 STAGES = ["sort", "faraday", "push", "filter", "ampere", "absorb", "inject", "zero", "total"]
 
 # (tile_r, tile_th, sort interval) tried by Sim.autotune by default
@@ -267,6 +267,13 @@ class Sim:
         out = np.zeros(2 * N)
         self._check(lib().pic_get_moments(self._h, MOM_GAUSS, _dp(out), out.size))
         return out[:N].reshape(self.nr + 1, self.nth + 1), out[N:].reshape(self.nr + 1, self.nth + 1)
+
+    def luminosity(self):
+        """Poynting luminosity (total field) through the sphere of each
+        radial half-node, computed on the device in FP64."""
+        out = np.zeros(self.nr)
+        self._check(lib().pic_get_moments(self._h, MOM_POYNTING, _dp(out), out.size))
+        return out
 
     def carry(self):
         out = np.zeros(self.nth + 1)

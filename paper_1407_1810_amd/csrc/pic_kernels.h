@@ -1637,6 +1637,46 @@ __global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict_
     }
 }
 
+// Spindown luminosity (Sec. 5.4): the Poynting flux of the total field
+// (plasma plus the analytic initial field at the current step) through the
+// sphere of each radial half-node, in FP64; one work-group per row
+// i = 0..nr-1.  Per meridional cell: E_theta averaged over its two radial
+// nodes, E_phi over its four corners, B_theta over its two meridional
+// nodes, B_phi at its own point, times the cell's face 2 pi rbar^2 dk_j.
+template <typename T>
+__global__ __launch_bounds__(256) void k_poynting(const T *__restrict__ Eth, const T *__restrict__ Eph,
+                                                  const T *__restrict__ Bth, const T *__restrict__ Bph, Layout L,
+                                                  Background bg, double inv_rl, double c,
+                                                  const double *__restrict__ rb, // rbar_i at [i + G]
+                                                  const double *__restrict__ Ar, // 2 pi rbar_i^2 at [i + G]
+                                                  const double *__restrict__ kc, // cos thetabar_j
+                                                  const double *__restrict__ sc, // sin thetabar_j
+                                                  const double *__restrict__ dk, // cos theta_j - cos theta_j+1
+                                                  double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const double r = rb[i + L.G], area = Ar[i + L.G];
+    double acc = 0.0;
+    for (int j = tid; j < L.nth; j += 256) {
+        double E[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
+        add_background<double>(bg, inv_rl, false, r, 1.0 / r, kc[j], sc[j], E, B);
+        const double eth = 0.5 * ((double)Eth[L.at(i, j)] + (double)Eth[L.at(i + 1, j)]) + E[1];
+        const double eph = 0.25 * ((double)Eph[L.at(i, j)] + (double)Eph[L.at(i + 1, j)] + (double)Eph[L.at(i, j + 1)] +
+                                   (double)Eph[L.at(i + 1, j + 1)]) + E[2];
+        const double bth = 0.5 * ((double)Bth[L.at(i, j)] + (double)Bth[L.at(i, j + 1)]) + B[1];
+        const double bph = (double)Bph[L.at(i, j)] + B[2];
+        acc += (eth * bph - eph * bth) * area * dk[j];
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) out[i] = c * red[0];
+}
+
 // Closed-surface flux of E out of the dual cell of node (i, j), i = 1..nr-1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gauss_flux(const T *__restrict__ Er, const T *__restrict__ Eth, Layout L,

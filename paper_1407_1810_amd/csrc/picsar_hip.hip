@@ -397,6 +397,7 @@ public:
                                   uint64_t *id, int64_t cap) = 0;
     virtual void counts(double *out) = 0;
     virtual void gauss(double *out) = 0;
+    virtual void luminosity(double *out) = 0;
     virtual void get_carry(double *out) = 0;
     virtual void set_carry(const double *in) = 0;
     virtual void set_step(int64_t step) = 0;
@@ -739,6 +740,27 @@ public:
         HIPCHK(hipFree(G));
     }
 
+    void luminosity(double *out) override
+    {
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        const double t = (double)c[kStep];
+        double *d = dev_alloc<double>((size_t)gd.nr);
+        try {
+            k_poynting<T><<<gd.nr, 256, 0, stream>>>(fld_[cETH], fld_[cEPH], fld_[cBTH], fld_[cBPH], L, rd_.bg,
+                                                     inv_light_cylinder(ph.omega, ph.t_spin, gd.c, t), gd.c, grb_,
+                                                     gA_r_, gkc_, gsb_, gdk_, d);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(out, d, sizeof(double) * gd.nr, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(d);
+            throw;
+        }
+        HIPCHK(hipFree(d));
+    }
+
     void get_carry(double *out) override
     {
         HIPCHK(hipMemcpyAsync(out, carry_, sizeof(double) * (gd.nth + 1), hipMemcpyDeviceToHost, stream));
@@ -962,6 +984,7 @@ private:
     const T *r_node_ = nullptr, *k_node_ = nullptr;
     const double *dkn_ = nullptr, *dsn_ = nullptr, *dAj_ = nullptr;
     const double *gA_r_ = nullptr, *gdkb_ = nullptr, *gA_t_ = nullptr, *gsb_ = nullptr;
+    const double *grb_ = nullptr, *gkc_ = nullptr, *gdk_ = nullptr;
     double rb0_ = 0.0;
     double stage_ms_[kStages] = {};
 
@@ -1110,6 +1133,15 @@ private:
         gdkb_ = upload<double>(dkb);
         gA_t_ = upload<double>(At);
         gsb_ = upload<double>(sb);
+        // FP64 tables of the luminosity diagnostic
+        std::vector<double> kc(nth), dk(nth);
+        for (int j = 0; j < nth; ++j) {
+            kc[j] = g.cth(j + 0.5);
+            dk[j] = k[j] - k[j + 1];
+        }
+        grb_ = upload<double>(rb);
+        gkc_ = upload<double>(kc);
+        gdk_ = upload<double>(dk);
     }
 
 };
@@ -1396,6 +1428,10 @@ pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap)
         case PIC_MOM_STAGE_MS:
             if (cap < 9) throw StatusError{PIC_EINVAL, "output buffer too small"};
             ctx->eng->stage_ms(out);
+            break;
+        case PIC_MOM_POYNTING:
+            if (cap < ctx->eng->gd.nr) throw StatusError{PIC_EINVAL, "output buffer too small"};
+            ctx->eng->luminosity(out);
             break;
         default:
             throw StatusError{PIC_EINVAL, "unknown moment"};

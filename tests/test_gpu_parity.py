@@ -93,6 +93,31 @@ def test_lds_and_global_paths_and_sort(prec):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
+def test_luminosity_moment(prec):
+    """The device's Poynting luminosity (PIC_MOM_POYNTING) against the
+    oracle's on the same state: a spinning monopole with injection after
+    12 steps (FP32 from identical input bits, one step)."""
+    from parity_util import oracle_from_sim
+    cfg, P = _small(nr=40, nth=36, pairs_per_cell=3, n_filt=2, bg="monopole", omega_frac=0.3, inject=1)
+    p = dict(cfg["params"], q_inj=cfg["params"]["q_inj"] * 0.5)
+    o, s = make_pair(p, P, prec, capacity=1 << 20)
+    if prec == "fp32":
+        s.step(11)
+        o = oracle_from_sim(s, p)
+        s.step(1)
+        o.step(1)
+    else:
+        s.step(12)
+        o.step(12)
+    Lg, Lo = s.luminosity(), o.luminosity()
+    scale = np.abs(Lo).max()
+    _say(f"{prec}: max |L| {scale:.3e}, worst difference {np.abs(Lg - Lo).max() / scale:.2e}")
+    assert scale > 0 and Lg.shape == (p["nr"],)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    assert np.abs(Lg - Lo).max() <= tol * scale
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_sort_groups_each_chunk_by_tile(prec):
     """The first sort puts the generator's shuffled particles in tile order:
     with exactly 64 particles per cell, tiles of 1 x 32 cells (one row of
