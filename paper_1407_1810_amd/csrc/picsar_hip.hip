@@ -1014,13 +1014,17 @@ private:
         HIPCHK(hipMemcpyAsync(c, ctr_, sizeof(unsigned long long) * kNumCounters, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
     }
-    // fixed-point scale of the LDS deposit from the largest |w| held;
+    // fixed-point scale of the LDS deposit from the largest |w| held,
+    // bounded so that it stays finite in T for vanishing weights (test
+    // particles): contributions of such weights then round to zero;
     // true when it changed
     bool set_dep_scale()
     {
         const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
-        const T sc = (T)(std::ldexp(1.0, fixed_bits<T>()) / qm);
-        const T inv = (T)(qm * std::ldexp(1.0, -fixed_bits<T>()));
+        const double top = std::ldexp(1.0, sizeof(T) == 4 ? 100 : 900);
+        const double sc_d = std::min(std::ldexp(1.0, fixed_bits<T>()) / qm, top);
+        const T sc = (T)sc_d;
+        const T inv = (T)(sc_d < top ? qm * std::ldexp(1.0, -fixed_bits<T>()) : 1.0 / top);
         const bool changed = sc != rd_.dep_scale || inv != rd_.dep_inv;
         rd_.dep_scale = sc;
         rd_.dep_inv = inv;
