@@ -827,6 +827,26 @@ __device__ __forceinline__ U at_slot(gptr<const U> a, uint32_t k)
     return *(gptr<const U>)((gptr<const char>)a + k * (uint32_t)sizeof(U));
 }
 
+// The same accesses with the non-temporal hint, for the particle streams
+// that a push reads once and writes once: they pass through L2 without
+// displacing what a chunk reads twice (its cells, read for the bounding box
+// and again by the loop, and the field planes shared by neighbouring chunks).
+template <typename U>
+__device__ __forceinline__ U ld_stream(gptr<U> a, uint32_t k)
+{
+    return __builtin_nontemporal_load((gptr<U>)((gptr<char>)a + k * (uint32_t)sizeof(U)));
+}
+template <typename U>
+__device__ __forceinline__ U ld_stream(gptr<const U> a, uint32_t k)
+{
+    return __builtin_nontemporal_load((gptr<const U>)((gptr<const char>)a + k * (uint32_t)sizeof(U)));
+}
+template <typename U>
+__device__ __forceinline__ void st_stream(gptr<U> a, uint32_t k, U v)
+{
+    __builtin_nontemporal_store(v, (gptr<U>)((gptr<char>)a + k * (uint32_t)sizeof(U)));
+}
+
 // The stored state of one particle, loaded ahead of its push, and the
 // state it leaves.
 template <typename T>
@@ -840,38 +860,40 @@ struct POut {
     T fx, fy, u0, u1, u2;
 };
 
+// Every slot of a chunk lies inside the arrays (a chunk starts below the
+// run's particle count, and a chunk of spare slots follows the capacity),
+// so the loads are unconditional; whether the slot holds a particle is
+// decided where the state is used, so that nothing waits for the loads
+// before then.
 template <typename T>
-__device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, uint32_t idx, uint32_t n)
+__device__ __forceinline__ PIn<T> load_particle(const PushArgs<T> &p, uint32_t idx)
 {
     PIn<T> a;
-    a.c = kDead;
-    a.fx = a.fy = a.w = a.u0 = a.u1 = a.u2 = (T)0;
-    if (idx < n) {
-        a.c = at_slot(p.cell, idx);
-        a.fx = at_slot(p.dx, idx);
-        a.fy = at_slot(p.dy, idx);
-        a.w = at_slot(p.w, idx);
-        a.u0 = at_slot(p.ur, idx);
-        a.u1 = at_slot(p.ut, idx);
-        a.u2 = at_slot(p.up, idx);
-    }
+    a.c = at_slot(p.cell, idx);
+    a.fx = ld_stream(p.dx, idx);
+    a.fy = ld_stream(p.dy, idx);
+    a.w = ld_stream(p.w, idx);
+    a.u0 = ld_stream(p.ur, idx);
+    a.u1 = ld_stream(p.ut, idx);
+    a.u2 = ld_stream(p.up, idx);
     return a;
 }
 
 // Every iteration of the push stores one state per lane (a lane past the
-// run's last particle writes its own slot, inside the chunk of spare slots
-// every particle array holds past the capacity), so that the loop issues
-// the same memory operations on every path and the wait for the next
-// particle's loads, issued before these stores, never waits for the stores.
+// run's last particle writes back what it loaded from its own slot, which
+// may lie in the chunk of spare slots every particle array holds past the
+// capacity), so that the loop issues the same memory operations on every
+// path and the wait for the next particle's loads, issued before these
+// stores, never waits for the stores.
 template <typename T>
 __device__ __forceinline__ void store_particle(const PushArgs<T> &p, uint32_t idx, const POut<T> &o)
 {
-    at_slot(p.dx, idx) = o.fx;
-    at_slot(p.dy, idx) = o.fy;
-    at_slot(p.ur, idx) = o.u0;
-    at_slot(p.ut, idx) = o.u1;
-    at_slot(p.up, idx) = o.u2;
-    at_slot(p.cell, idx) = o.c;
+    st_stream(p.dx, idx, o.fx);
+    st_stream(p.dy, idx, o.fy);
+    st_stream(p.ur, idx, o.u0);
+    st_stream(p.ut, idx, o.u1);
+    st_stream(p.up, idx, o.u2);
+    st_stream(p.cell, idx, o.c);
 }
 
 // One particle: gather, push, move with cancellation-free local increments,
@@ -983,6 +1005,17 @@ __device__ inline POut<T> push_particle(const PushArgs<T> &p, const V &view, con
         o.c = pack_cell(ni, nj);
     }
     return o;
+}
+
+// The particle loaded from chunk slot idx (a particle if idx < n and its
+// cell is not the dead mark): pushed, and its new state stored.
+template <typename T, typename V, typename D>
+__device__ __forceinline__ void push_slot(const PushArgs<T> &p, const V &view, const D &dep, const PIn<T> &in,
+                                          uint32_t idx, uint32_t n)
+{
+    POut<T> o{in.c, in.fx, in.fy, in.u0, in.u1, in.u2};
+    if (idx < n && in.c != kDead) o = push_particle(p, view, dep, in);
+    store_particle(p, idx, o);
 }
 
 __device__ inline int wave_min(int v)
@@ -1175,18 +1208,15 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             const LdsView<T> view{sm, srn, i0, j0, C};
             const LdsDep<T> dep{sd, sl, i0, j0, C, R.dep_scale};
             // the next particle's state is loaded while this one is pushed
-            PIn<T> nxt = load_particle(p, chunk_slot(tid, 0), n32);
+            PIn<T> nxt = load_particle(p, chunk_slot(tid, 0));
 #pragma unroll 1
             for (int q0 = 0; q0 < PPT; ++q0) {
                 // the iteration index, opaque to the compiler, so that it does
                 // not turn the seven array accesses into seven 64-bit pointers
                 const int q = __builtin_amdgcn_readfirstlane(q0);
                 const PIn<T> cur = nxt;
-                const uint32_t idx = chunk_slot(tid, q);
-                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(tid, q + 1), n32);
-                POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
-                if (cur.c != kDead) o = push_particle(p, view, dep, cur);
-                store_particle(p, idx, o);
+                if (q + 1 < PPT) nxt = load_particle(p, chunk_slot(tid, q + 1));
+                push_slot(p, view, dep, cur, chunk_slot(tid, q), n32);
             }
             __syncthreads();
             {
@@ -1219,10 +1249,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
             for (int q0 = 0; q0 < PPT; ++q0) {
                 const int q = __builtin_amdgcn_readfirstlane(q0);
                 const uint32_t idx = chunk_slot(tid, q);
-                const PIn<T> cur = load_particle(p, idx, n32);
-                POut<T> o{cur.c, cur.fx, cur.fy, cur.u0, cur.u1, cur.u2};
-                if (cur.c != kDead) o = push_particle(p, view, dep, cur);
-                store_particle(p, idx, o);
+                push_slot(p, view, dep, load_particle(p, idx), idx, n32);
             }
         }
     }
