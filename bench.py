@@ -211,12 +211,15 @@ def cpu_baseline(cfg, P, seconds=12.0, max_threads=16):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    # the timed windows span whole sort intervals (32 FP32 steps after 5
+    # warm-up ones hold the sorts of steps 16 and 32; 16 FP64 steps after 2
+    # hold that of step 16), so that the sort weighs in at its real share
+    ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=str, default="4x8")
+    ap.add_argument("--tile", type=str, default="4x16")
     ap.add_argument("--sort-interval", type=int, default=16)
     ap.add_argument("--ppt", type=int, default=16, help="particles per thread of a push work-group (4, 8, 16)")
     ap.add_argument("--no-batched", action="store_true")
@@ -241,6 +244,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is not sharded across "
               f"GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    # the copy is timed through torch, which must initialise the device before
+    # the library's own HIP context exists
+    copy_gbs = measured_copy_peak()
+    log(f"plain 1 GiB device copy: {copy_gbs:.0f} GB/s")
     from paper_1407_1810_amd import workloads as W
     cfg = W.config(2)
     p = cfg["params"]
@@ -249,6 +256,10 @@ def main():
     n = len(P["x"])
     log(f"generated {n} particles for {cfg['name']} in {time.perf_counter() - t0:.1f} s")
     tile = tuple(int(v) for v in args.tile.split("x"))
+    for k, name in ((args.steps, "--steps"), (args.fp64_steps, "--fp64-steps")):
+        if args.sort_interval > 0 and k % args.sort_interval:
+            log(f"note: {name} {k} is not a multiple of the sort interval {args.sort_interval}; the timed "
+                f"window does not hold the sort at its steady-state share")
     r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, args.sort_interval, args.ppt)
     r64 = None
     if not args.no_fp64:
@@ -271,7 +282,6 @@ def main():
     if "valu_busy" in prof:
         utilisation = {"valu_busy": float(prof["valu_busy"]),
                        "valu_instr_per_particle": float(prof["valu_instr_per_particle"])}
-    copy_gbs = measured_copy_peak()
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, P)
     out = {
         "metric": "particle-steps/sec (push+deposit+field), FP32 and batched vs FP64 GPU",

@@ -1,5 +1,5 @@
 """GPU parity at the benchmark sizes, in the launch configuration bench.py
-times (sort tile 4 x 8, sort every 16 steps, 16 particles per thread), against
+times (sort tile 4 x 16, sort every 16 steps, 16 particles per thread), against
 the FP64 oracle running the same step on the host cores:
 
   * the dipole rotator, 1024 x 1024 cells, 64 particles per cell (67.1M),
@@ -36,7 +36,7 @@ from parity_util import TOL, compare_fields, oracle_from_sim, round_to_storage
 
 pytestmark = pytest.mark.gpu
 
-TILE, SORT_INTERVAL, PPT = (4, 8), 16, 16
+TILE, SORT_INTERVAL, PPT = (4, 16), 16, 16
 
 
 def _say(*a):
