@@ -255,6 +255,13 @@ __global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ ru
     }
 }
 
+// The updates of a thread's rows are formed first and stored together, so
+// that no load waits behind a store it cannot be proven not to alias.  The
+// loads are unconditional, at a row clamped to nr and columns clamped into
+// the tables (rows -1 and nr + 1 are ghost rows, and column nth + 1 is the
+// next row's first entry), so that all of them are issued before the first
+// wait; only the stores are conditional, and where they happen the indices
+// were not clamped.
 template <typename T>
 __device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr<const T> __restrict__ Eth,
                                              gptr<const T> __restrict__ Eph, gptr<T> __restrict__ Br,
@@ -264,23 +271,30 @@ __device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr
     const int nr = L.nr, nth = L.nth;
     const gptr<const T> s = glb(m.s), invr = glb(m.invr), icBr = glb(m.icBr), rn = glb(m.r_node),
                         idr2 = glb(m.idr2), dr = glb(m.dr), idth = glb(m.idth);
+    T br[kFieldRows], bth[kFieldRows], bph[kFieldRows];
+#pragma unroll
+    for (int rs = 0; rs < kFieldRows; ++rs) {
+        const int i = min(i0 + rs, nr);
+        {
+            const T circ = Eph[L.at(i, j)] * s[j] - Eph[L.at(i, j + 1)] * s[min(j + 1, nth)];
+            br[rs] = Br[L.at(i, j)] + hc * circ * invr[i] * icBr[j];
+        }
+        {
+            const T circ = Eph[L.at(i + 1, j)] * rn[i + 1 + L.G] - Eph[L.at(i, j)] * rn[i + L.G];
+            bth[rs] = Bth[L.at(i, j)] + hc * circ * idr2[i];
+        }
+        {
+            const T a = Eth[L.at(i, j)] * rn[i + L.G] - Eth[L.at(i + 1, j)] * rn[i + 1 + L.G];
+            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * dr[i] * idth[j];
+            bph[rs] = Bph[L.at(i, j)] + hc * (a - b) * idr2[i];
+        }
+    }
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
-        if (i > nr) break;
-        if (i >= 1 && i < nr && j < nth) {
-            const T circ = Eph[L.at(i, j)] * s[j] - Eph[L.at(i, j + 1)] * s[j + 1];
-            Br[L.at(i, j)] += hc * circ * invr[i] * icBr[j];
-        }
-        if (i < nr && j >= 1 && j < nth) {
-            const T circ = Eph[L.at(i + 1, j)] * rn[i + 1 + L.G] - Eph[L.at(i, j)] * rn[i + L.G];
-            Bth[L.at(i, j)] += hc * circ * idr2[i];
-        }
-        if (i < nr && j < nth) {
-            const T a = Eth[L.at(i, j)] * rn[i + L.G] - Eth[L.at(i + 1, j)] * rn[i + 1 + L.G];
-            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * dr[i] * idth[j];
-            Bph[L.at(i, j)] += hc * (a - b) * idr2[i];
-        }
+        if (i >= 1 && i < nr && j < nth) Br[L.at(i, j)] = br[rs];
+        if (i < nr && j >= 1 && j < nth) Bth[L.at(i, j)] = bth[rs];
+        if (i < nr && j < nth) Bph[L.at(i, j)] = bph[rs];
     }
 }
 
@@ -299,7 +313,8 @@ __global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ r
                     glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j, hc_frac * R.c);
 }
 
-// E += (c circulation(B) - F) / area, then the lossy-layer factor on E.
+// E += (c circulation(B) - F) / area, then the lossy-layer factor on E;
+// unconditional loads at clamped indices, conditional stores, as for B.
 template <typename T>
 __device__ __forceinline__ void ampere_rows(gptr<const T> __restrict__ Br, gptr<const T> __restrict__ Bth,
                                             gptr<const T> __restrict__ Bph, gptr<const T> __restrict__ Fr,
@@ -312,27 +327,34 @@ __device__ __forceinline__ void ampere_rows(gptr<const T> __restrict__ Br, gptr<
     const gptr<const T> sb = glb(m.sb), invrb = glb(m.invrb), invA = glb(m.invA), idkb = glb(m.idkb),
                         ab_half = glb(m.ab_half), rb = glb(m.rb), isb2pi = glb(m.isb2pi), idrb2 = glb(m.idrb2),
                         ab_int = glb(m.ab_int), drb = glb(m.drb), idthb = glb(m.idthb);
+    T er[kFieldRows], eth[kFieldRows], eph[kFieldRows];
+    const T sbj = sb[j], sbw = sb[max(j - 1, 0)];
+#pragma unroll
+    for (int rs = 0; rs < kFieldRows; ++rs) {
+        const int i = min(i0 + rs, nr);
+        const size_t e = L.at(i, j);
+        const T bph = Bph[e], bph_w = Bph[L.at(i, j - 1)]; // column -1 is the previous row's last entry
+        {
+            const T t1 = j < nth ? sbj * bph : (T)0;
+            const T t0 = j > 0 ? sbw * bph_w : (T)0;
+            er[rs] = (Er[e] + (c * (t1 - t0) * invrb[i] - Fr[e] * invA[i]) * idkb[j]) * ab_half[i];
+        }
+        {
+            const T circ = rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - rb[i + L.G] * bph;
+            eth[rs] = (Eth[e] + (c * circ - Fth[e] * isb2pi[j]) * idrb2[i]) * ab_int[i];
+        }
+        {
+            const T a = rb[i + L.G] * Bth[e] - rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
+            const T b = (Br[e] - Br[L.at(i, j - 1)]) * drb[i] * idthb[j];
+            eph[rs] = (Eph[e] + (c * (a - b) - Fph[e] * idthb[j]) * idrb2[i]) * ab_int[i];
+        }
+    }
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
-        if (i > nr) break;
-        if (i < nr) {
-            const T t1 = j < nth ? sb[j] * Bph[L.at(i, j)] : (T)0;
-            const T t0 = j > 0 ? sb[j - 1] * Bph[L.at(i, j - 1)] : (T)0;
-            const size_t e = L.at(i, j);
-            Er[e] = (Er[e] + (c * (t1 - t0) * invrb[i] - Fr[e] * invA[i]) * idkb[j]) * ab_half[i];
-        }
-        if (i >= 1 && i < nr && j < nth) {
-            const T circ = rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - rb[i + L.G] * Bph[L.at(i, j)];
-            const size_t e = L.at(i, j);
-            Eth[e] = (Eth[e] + (c * circ - Fth[e] * isb2pi[j]) * idrb2[i]) * ab_int[i];
-        }
-        if (i >= 1 && i < nr && j >= 1 && j < nth) {
-            const T a = rb[i + L.G] * Bth[L.at(i, j)] - rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
-            const T b = (Br[L.at(i, j)] - Br[L.at(i, j - 1)]) * drb[i] * idthb[j];
-            const size_t e = L.at(i, j);
-            Eph[e] = (Eph[e] + (c * (a - b) - Fph[e] * idthb[j]) * idrb2[i]) * ab_int[i];
-        }
+        if (i < nr) Er[L.at(i, j)] = er[rs];
+        if (i >= 1 && i < nr && j < nth) Eth[L.at(i, j)] = eth[rs];
+        if (i >= 1 && i < nr && j >= 1 && j < nth) Eph[L.at(i, j)] = eph[rs];
     }
 }
 
@@ -363,15 +385,23 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
     if (j > L.nth) return;
     const gptr<const T> ab_int = glb(R.m.ab_int), ab_half = glb(R.m.ab_half);
     const gptr<T> Br = glb(R.fld[cBR]), Bth = glb(R.fld[cBTH]), Bph = glb(R.fld[cBPH]);
+    const int i0 = L.nr - R.absorb_cells - 1 + q.i;
+    // all loads of the thread's rows (unconditional, at a row clamped into
+    // 0..nr) before its conditional stores
+    T br[kFieldRows], bth[kFieldRows], bph[kFieldRows];
+#pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
-        const int i = L.nr - R.absorb_cells - 1 + q.i + rs;
-        if (i > L.nr) return;
-        if (i < 0) continue;
-        if (j < L.nth) Br[L.at(i, j)] *= ab_int[i];
-        if (i < L.nr) {
-            Bth[L.at(i, j)] *= ab_half[i];
-            if (j < L.nth) Bph[L.at(i, j)] *= ab_half[i];
-        }
+        const int i = min(max(i0 + rs, 0), L.nr);
+        br[rs] = Br[L.at(i, j)] * ab_int[i];
+        bth[rs] = Bth[L.at(i, j)] * ab_half[i];
+        bph[rs] = Bph[L.at(i, j)] * ab_half[i];
+    }
+#pragma unroll
+    for (int rs = 0; rs < kFieldRows; ++rs) {
+        const int i = i0 + rs;
+        if (i >= 0 && i <= L.nr && j < L.nth) Br[L.at(i, j)] = br[rs];
+        if (i >= 0 && i < L.nr) Bth[L.at(i, j)] = bth[rs];
+        if (i >= 0 && i < L.nr && j < L.nth) Bph[L.at(i, j)] = bph[rs];
     }
 }
 
@@ -417,6 +447,8 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
                                                 const int *__restrict__ off)
 {
     constexpr int NR = kFiltTR + 2 * H, NC = kFiltTC + 2 * H, N = NR * NC;
+    constexpr int KN = (N + 255) / 256, KO = kFiltTR * kFiltTC / 256; // entries per thread: tile + halo, tile
+    static_assert(kFiltTR * kFiltTC % 256 == 0, "the filter tile is a whole number of 256-entry sweeps");
     __shared__ T sa[N], sb[N], st[N];
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
@@ -433,39 +465,61 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const gptr<const T> src = glb((const T *)R.fld[cFR + comp]);
     const gptr<T> dst = glb(R.ftmp[comp]);
     const int tid = threadIdx.x;
-    for (int e = tid; e < N; e += 256) {
-        const int li = e / NC, lj = e - li * NC;
-        const int i = i0 + li, j = j0 + lj;
-        sa[e] = (i >= first && i <= last && j >= 0 && j < ncol) ? src[L.at(i, j)] : (T)0;
+    // The entries of this thread, e = tid + 256 k, each with flags formed once:
+    // bit 0 the theta half is formed there (inside the array, off the tile's
+    // edge columns), bit 1 j > 0, bit 2 j + 1 < ncol, bits 3 and 4 the axis
+    // node j = 0 or nth mirrored onto j = 1 or nth - 1 (integer j), bits 5
+    // and 6 the odd parity at j = 0 or nth - 1 (half-integer j), bit 7 the
+    // radial half is formed there (inside the array, off the edge rows).
+    unsigned fl[KN];
+    {
+        // every load of the tile and its halo issued before the first LDS write
+        T v[KN];
+#pragma unroll
+        for (int k = 0; k < KN; ++k) {
+            const int e = tid + 256 * k;
+            const int li = e / NC, lj = e - li * NC;
+            const int i = i0 + li, j = j0 + lj;
+            const bool in = e < N && i >= first && i <= last && j >= 0 && j < ncol;
+            v[k] = in ? src[L.at(i, j)] : (T)0;
+            fl[k] = (unsigned)(in && lj >= 1 && lj < NC - 1) | (unsigned)(j > 0) << 1 | (unsigned)(j + 1 < ncol) << 2 |
+                    (unsigned)(kind == 0 && j == 1) << 3 | (unsigned)(kind == 0 && j == nth - 1) << 4 |
+                    (unsigned)(kind == 1 && j == 0) << 5 | (unsigned)(kind == 1 && j == nth - 1) << 6 |
+                    (unsigned)(in && li >= 1 && li < NR - 1) << 7;
+        }
+#pragma unroll
+        for (int k = 0; k < KN; ++k)
+            if (tid + 256 * k < N) sa[tid + 256 * k] = v[k];
     }
     T *a = sa, *b = sb;
     for (int p = 0; p < passes; ++p) {
         __syncthreads();
-        for (int e = tid; e < N; e += 256) { // theta half
-            const int li = e / NC, lj = e - li * NC;
-            const int i = i0 + li, j = j0 + lj;
+#pragma unroll
+        for (int k = 0; k < KN; ++k) { // theta half
+            const int e = tid + 256 * k;
+            if (e >= N) break;
+            const unsigned f = fl[k];
             T v = (T)0;
-            if (lj >= 1 && lj < NC - 1 && i >= first && i <= last && j >= 0 && j < ncol) {
+            if (f & 1u) {
                 const T *row = a + e; // row[0] is column j
-                v = (T)0.5 * row[0];
-                if (j > 0) v += (T)0.25 * row[-1];
-                if (j + 1 < ncol) v += (T)0.25 * row[1];
-                if (kind == 0) {
-                    if (j == 1) v += (T)0.25 * row[-1];      // the axis node j = 0, mirrored
-                    if (j == nth - 1) v += (T)0.25 * row[1]; // the axis node j = nth, mirrored
-                } else {
-                    if (j == 0) v -= (T)0.25 * row[0];       // odd parity across the axis
-                    if (j == nth - 1) v -= (T)0.25 * row[0];
-                }
+                const T r0 = row[0], rm = row[-1], rp = row[1];
+                v = (T)0.5 * r0;
+                v += (f & 2u) ? (T)0.25 * rm : (T)0;
+                v += (f & 4u) ? (T)0.25 * rp : (T)0;
+                v += (f & 8u) ? (T)0.25 * rm : (T)0;  // the axis node j = 0, mirrored
+                v += (f & 16u) ? (T)0.25 * rp : (T)0; // the axis node j = nth, mirrored
+                v -= (f & 32u) ? (T)0.25 * r0 : (T)0; // odd parity across the axis
+                v -= (f & 64u) ? (T)0.25 * r0 : (T)0;
             }
             st[e] = v;
         }
         __syncthreads();
-        for (int e = tid; e < N; e += 256) { // radial half
-            const int li = e / NC, lj = e - li * NC;
-            const int i = i0 + li, j = j0 + lj;
+#pragma unroll
+        for (int k = 0; k < KN; ++k) { // radial half
+            const int e = tid + 256 * k;
+            if (e >= N) break;
             T v = (T)0;
-            if (li >= 1 && li < NR - 1 && i >= first && i <= last && j >= 0 && j < ncol) {
+            if (fl[k] & 128u) {
                 v = (T)0.5 * st[e];
                 v += (T)0.25 * st[e - NC];
                 v += (T)0.25 * st[e + NC];
@@ -477,7 +531,9 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
         b = t;
     }
     __syncthreads();
-    for (int e = tid; e < kFiltTR * kFiltTC; e += 256) {
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int e = tid + 256 * k;
         const int ci = e / kFiltTC, cj = e - ci * kFiltTC;
         const int i = i0 + H + ci, j = j0 + H + cj;
         if (i <= last && j < ncol) dst[L.at(i, j)] = a[(H + ci) * NC + H + cj];
