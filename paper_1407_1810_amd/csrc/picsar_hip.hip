@@ -507,7 +507,7 @@ public:
         R.cd = gd.c;
         for (int s = 0; s < 2; ++s) {
             // one push chunk of spare slots past the capacity takes the
-            // stores of lanes past the last particle
+            // loads and stores of lanes past the last particle
             cell_[s] = dalloc<uint32_t>(cap_ + kMaxChunk);
             R.cell[s] = cell_[s];
             for (int a = 0; a < 6; ++a) {

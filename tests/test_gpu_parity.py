@@ -93,6 +93,30 @@ def test_lds_and_global_paths_and_sort(prec):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("ppt", [4, 16])
+def test_capacity_equal_to_count_ragged_chunks(prec, ppt):
+    """Capacity exactly the particle count, which is no multiple of a push
+    chunk (256 x particles per thread): the lanes of the last chunk past the
+    count load and store in the spare slots past the capacity and leave the
+    particles alone.  Sorted (LDS) and unsorted steps against the oracle."""
+    cfg, P = _small(nr=40, nth=36, pairs_per_cell=3, n_filt=2, absorb_cells=5, theta_T=0.3)
+    p = cfg["params"]
+    P["x"][1::4] = np.clip(P["x"][1::4] + 0.41, 0.0, p["nr"] - 1e-9)
+    n = len(P["x"])
+    assert n % (256 * ppt) != 0
+    _say("capacity = count", prec, ppt, n)
+    o, s = make_pair(p, P, prec, capacity=n, chunk_ppt=ppt, tile=(4, 4), sort_interval=2)
+    t = TOL[prec]
+    for k in range(3):
+        o.step(1)
+        s.step(1)
+        sc = 1.0 if k == 0 else 10.0 * (k + 1)
+        compare_fields(o, s, t["field"] * sc)
+        compare_particles(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
+    assert s.counts()["live"] == o.n
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_luminosity_moment(prec):
     """The device's Poynting luminosity (PIC_MOM_POYNTING) against the
     oracle's on the same state: a spinning monopole with injection after
