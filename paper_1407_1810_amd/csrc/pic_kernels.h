@@ -729,36 +729,26 @@ struct LdsView {
 
 // Deposit planes in LDS hold fixed point, so that integer LDS atomics (much
 // faster than floating-point ones) accumulate the contributions exactly and
-// in any order.  Every contribution v is at most max|w| in magnitude, and a
-// chunk of at most 4096 particles adds at most four contributions to an
-// entry, 2^14 in all.
-//  FP32: one 64-bit plane per component, v stored as q = round(v * 2^35 /
+// in any order.  Every contribution v is at most max|w| in magnitude.
+//  FP32: one 64-bit plane per component, v stored as round(v * 2^40 /
 //        max|w|), rounded to the integer through FP64 with the 1.5 * 2^52
-//        shift.  The shifted value's bits, 0x4338 * 2^48 + q, are added as
-//        they are: the constant is a multiple of 2^51, so the low 51 bits of
-//        an entry hold the sum of its q modulo 2^51, and that sum, below
-//        2^49 + 2^13 in magnitude, is read back by sign extension from bit
-//        50.  The quantum, 3e-11 max|w|, lies below the FP32 rounding of
-//        contributions down to 1e-3 max|w| (small azimuthal steps, plasma
-//        particles beside heavier injected ones) and far below that of the
-//        face charges they add up to.
+//        shift; the quantum, 1e-12 max|w|, lies below the FP32 rounding of
+//        contributions far smaller than max|w| (small azimuthal steps,
+//        plasma particles beside heavier injected ones).
 //  FP64: x = v * 2^48 / max|w| is split into its nearest integer (a 64-bit
 //        plane, converted exactly with the 1.5 * 2^52 shift, valid below
 //        2^51) and the exact remainder in [-1/2, 1/2] in units of 2^-16 (a
 //        32-bit plane): the quantum is 2^-64 max|w|, far below FP64 rounding
-//        even where the charges of co-located pairs cancel.  The sums stay
-//        below 2^62 in the 64-bit plane and 2^31 in the 32-bit one.
+//        even where the charges of co-located pairs cancel.
+// A chunk of at most 4096 particles adds at most four contributions to an
+// entry: below 2^54 (FP32) or 2^62 (FP64) in the 64-bit planes and 2^31 in
+// the 32-bit ones.
 template <typename T>
 constexpr int fixed_bits();
 template <>
-constexpr int fixed_bits<float>() { return 35; }
+constexpr int fixed_bits<float>() { return 40; }
 template <>
 constexpr int fixed_bits<double>() { return 48; }
-// The FP32 plane's sum of the integers added to an entry, from its low 51 bits
-__device__ __forceinline__ long long fixed_sum51(long long raw)
-{
-    return (long long)((unsigned long long)raw << 13) >> 13;
-}
 constexpr double kLoScale = 65536.0; // units of the FP64 remainder plane per unit of the main plane
 
 template <typename T>
@@ -778,8 +768,9 @@ struct LdsDep<float> {
     __device__ float unit() const { return scale; }
     __device__ void add(int c, int e, float v) const
     {
-        const double sh = (double)v + 6755399441055744.0; // 1.5 * 2^52: 0x4338 * 2^48 + round(v)
-        atomicAdd((unsigned long long *)&s[c * P + e], (unsigned long long)__double_as_longlong(sh));
+        const double sh = (double)v + 6755399441055744.0; // 1.5 * 2^52
+        const long long q = __double_as_longlong(sh) - 0x4338000000000000ll;
+        atomicAdd((unsigned long long *)&s[c * P + e], (unsigned long long)q);
     }
 };
 
@@ -1298,8 +1289,7 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
                             if (v != 0 || l != 0)
                                 atomic_add(p.f.c[cFR + comp] + g, ((T)v + (T)l * (T)(1.0 / kLoScale)) * inv);
                         } else {
-                            const long long q = fixed_sum51(v);
-                            if (q != 0) atomic_add(p.f.c[cFR + comp] + g, (T)q * inv);
+                            if (v != 0) atomic_add(p.f.c[cFR + comp] + g, (T)v * inv);
                         }
                     }
                     fr += dr;
