@@ -208,6 +208,45 @@ def cpu_baseline(cfg, P, seconds=12.0, max_threads=16):
                        f"{steps} steps, {nthreads} threads")
 
 
+def oracle_timing(seconds=8.0, max_threads=16):
+    """The FP64 oracle on the host cores, one thread and all of them, on
+    bounded samples of the four single-run workloads: the 64 x 64 plain FP64
+    method in full; the 512 x 512 monopole rotator's first steps from its
+    empty start (injection only); the 1024 x 1024 dipole rotator with 8 of
+    its 32 pairs per cell; the 2048 x 2048 precision stress with 3 of its 24.
+    Each entry runs until `seconds` have passed or its step count is done;
+    the rate counts the live particles at the start of each step."""
+    from oracle import oracle as O
+    from paper_1407_1810_amd import workloads as W
+    O.build()
+    allt = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    plan = [(0, None, 100), (1, None, 200), (2, 8, 50), (3, 3, 20)]
+    rows = []
+    for k, ppc, max_steps in plan:
+        cfg = W.config(k)
+        p = cfg["params"]
+        pairs = cfg.get("pairs_per_cell", 0) if ppc is None else ppc
+        P = W.pair_plasma(p, pairs, cfg["theta_T"], cfg["weight"], cfg["seed"]) if pairs else None
+        for threads in sorted({1, allt}):
+            O.set_threads(threads)
+            o = O.Oracle(p)
+            if P is not None:
+                o.add_particles(*[P[q] for q in ("x", "y", "ur", "ut", "up", "w")])
+            psteps, steps, t0 = 0, 0, time.perf_counter()
+            while steps < max_steps and time.perf_counter() - t0 < seconds:
+                psteps += o.n
+                o.step(1)
+                steps += 1
+            el = time.perf_counter() - t0
+            rows.append(dict(workload=cfg["name"], pairs_per_cell=pairs, threads=threads, steps=steps,
+                             particles_end=o.n, seconds=round(el, 2), ms_per_step=1e3 * el / steps,
+                             value=psteps / el))
+            log(f"[oracle] {cfg['name']} ({pairs} pairs/cell) {threads} threads: {steps} steps, "
+                f"{psteps / el:.3e} particle-steps/s")
+            del o
+    return dict(unit="particle-steps/s", kind="oracle", host_threads=allt, rows=rows)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,9 +266,14 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-warmup", type=int, default=50)
     ap.add_argument("--batched-tune-steps", type=int, default=4)
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle on samples of the four single-run workloads (host cores)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
