@@ -183,10 +183,12 @@ __global__ void k_fill(T *__restrict__ p, size_t n, T v)
 // ------------------------------------------------------------------
 
 // One thread: count the particle-steps this step advances, decide per run
-// whether it sorts, and lay the sort spans of the sorting runs end to end.
+// whether it sorts (never when may_sort is 0: the launch sequence of a step
+// without the sort kernels), and lay the sort spans of the sorting runs end
+// to end.
 template <typename T>
 __global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int span,
-                             unsigned long long *__restrict__ span_off)
+                             unsigned long long *__restrict__ span_off, int may_sort)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     unsigned long long acc = 0;
@@ -194,7 +196,7 @@ __global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int
         const gptr<unsigned long long> c = glb(runs[r].ctr);
         c[kPartSteps] += c[kTotal] - c[kDeadSinceSort];
         const int K = runs[r].sort_interval;
-        const bool now = K > 0 && (c[kNeedSort] != 0 || c[kStep] % (unsigned long long)K == 0);
+        const bool now = may_sort && K > 0 && (c[kNeedSort] != 0 || c[kStep] % (unsigned long long)K == 0);
         c[kSortNow] = now ? 1ull : 0ull;
         span_off[r] = acc;
         if (now) acc += (c[kTotal] + span - 1) / span;

@@ -116,6 +116,22 @@ private:
 // ------------------------------------------------------------------
 enum { kMapGrid = 0, kMapFilter, kMapAbsorb, kMapZero, kMapKeys, kMaps };
 
+// The host's record of one run's sort schedule: its sort interval, the
+// index of its next step and whether particles arrived since its last sort
+// (the device counters kStep and kNeedSort, set alike by every host action
+// that sets those, and advanced here step by step by the device's rule).
+struct SortSched {
+    int K;
+    uint64_t *step;
+    bool *need;
+    bool due() const { return K > 0 && (*need || *step % (uint64_t)K == 0); }
+    void advance(bool sorted) const
+    {
+        if (sorted && due()) *need = false;
+        ++*step;
+    }
+};
+
 template <typename T>
 class Plan {
 public:
@@ -126,12 +142,14 @@ public:
 
     void reset()
     {
-        if (exec_) (void)hipGraphExecDestroy(exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
+        for (int g = 0; g < 2; ++g) {
+            if (exec_[g]) (void)hipGraphExecDestroy(exec_[g]);
+            if (graph_[g]) (void)hipGraphDestroy(graph_[g]);
+            exec_[g] = nullptr;
+            graph_[g] = nullptr;
+        }
         if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
         for (void *p : allocs_) (void)hipFree(p);
-        exec_ = nullptr;
-        graph_ = nullptr;
         cap_stream_ = nullptr;
         allocs_.clear();
     }
@@ -203,20 +221,28 @@ public:
     }
 
     // n steps on stream s: eagerly with stage events when a timer is
-    // given, else by replaying the captured graph of one step
-    void run(int n, hipStream_t s, StageTimer *timer)
+    // given, else by replaying the captured graph of one step.  A step in
+    // which no run sorts (by the host's record of each run's step index and
+    // pending sort, which follows the device's rule) leaves the sort kernels
+    // out and tells the step's bookkeeping that no run sorts; were the
+    // record wrong, a sort would only come later, never half done.
+    void run(int n, hipStream_t s, StageTimer *timer, const std::vector<SortSched> &sched)
     {
         if (n <= 0) return;
-        if (timer) {
-            timer->begin(n);
-            for (int q = 0; q < n; ++q) {
+        if (timer) timer->begin(n);
+        for (int q = 0; q < n; ++q) {
+            bool sort = false;
+            for (const SortSched &r : sched) sort = sort || r.due();
+            sort = sort && any_sort_;
+            if (timer) {
                 timer->next_step(q);
-                enqueue(s, timer);
+                enqueue(s, timer, sort);
+            } else {
+                if (!exec_[sort]) capture(sort);
+                HIPCHK(hipGraphLaunch(exec_[sort], s));
             }
-            return;
+            for (const SortSched &r : sched) r.advance(sort);
         }
-        if (!exec_) capture();
-        for (int q = 0; q < n; ++q) HIPCHK(hipGraphLaunch(exec_, s));
     }
 
 private:
@@ -231,8 +257,8 @@ private:
     size_t shm_ = 0;
     int sort_blocks_ = 1, push_grid_ = 8;
     hipStream_t cap_stream_ = nullptr;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t exec_ = nullptr;
+    hipGraph_t graph_[2] = {};      // one step without, and with, the sort kernels
+    hipGraphExec_t exec_[2] = {};
 
     template <typename U>
     U *alloc(size_t n)
@@ -243,20 +269,20 @@ private:
     }
     const int *map(int m) const { return maps_ + (size_t)m * (n_ + 1); }
 
-    void capture()
+    void capture(bool sort)
     {
         if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue(cap_stream_, nullptr);
+            enqueue(cap_stream_, nullptr, sort);
         } catch (...) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(cap_stream_, &g);
             if (g) (void)hipGraphDestroy(g);
             throw;
         }
-        HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
-        HIPCHK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        HIPCHK(hipStreamEndCapture(cap_stream_, &graph_[sort]));
+        HIPCHK(hipGraphInstantiate(&exec_[sort], graph_[sort], nullptr, nullptr, 0));
     }
 
     void mark(StageTimer *t, hipStream_t s, int q, bool start)
@@ -266,15 +292,16 @@ private:
 
     // The launches of one step (order of Sec. 3 and App. A: half Faraday,
     // push and deposit, half Faraday, filter, Ampere, lossy layer, then
-    // injection), preceded by the counting sort when a run is due.
-    void enqueue(hipStream_t s, StageTimer *t)
+    // injection), preceded by the counting sort when `sort` is set (the
+    // device then sorts the runs that are due).
+    void enqueue(hipStream_t s, StageTimer *t, bool sort)
     {
         const dim3 blk2(64, 4);
         mark(t, s, kStTotal, true);
         mark(t, s, kStSort, true);
-        k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_);
+        k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_, sort ? 1 : 0);
         HIPCHK(hipGetLastError());
-        if (any_sort_) {
+        if (sort) {
             if (tot_[kMapKeys] > 0) k_sort_zero<T><<<tot_[kMapKeys], 256, 0, s>>>(runs_, n_, map(kMapKeys));
             k_sort_hist<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
             k_sort_scan<T><<<n_, 1024, 0, s>>>(runs_);
@@ -521,6 +548,8 @@ public:
         ctr_ = dalloc<unsigned long long>(kNumCounters);
         fill(ctr_, kNumCounters, 0ull);
         fill(ctr_ + kNeedSort, 1, 1ull); // the first step sorts
+        sched_step_ = 0;
+        sched_need_ = true;
         R.ctr = ctr_;
         status_ = dalloc<int>(1);
         fill(status_, 1, 0);
@@ -544,6 +573,8 @@ public:
 
     const RunDev<T> &run_desc() const { return rd_; }
     int ppt() const { return ppt_; }
+    // this run's sort schedule as the host records it (see SortSched)
+    SortSched sched() { return SortSched{rd_.sort_interval, &sched_step_, &sched_need_}; }
 
     void inject(int64_t n, const double *x, const double *y, const double *ur, const double *ut, const double *up,
                 const double *w, const uint64_t *id) override
@@ -593,6 +624,7 @@ public:
         HIPCHK(hipMemcpyAsync(ctr_ + kTotal, &upd[0], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(ctr_ + kNeedSort, &upd[1], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
+        sched_need_ = true;
         if (set_dep_scale()) {
             plan_.upload({rd_}, stream);
             ++version;
@@ -601,7 +633,7 @@ public:
 
     void step(int n) override
     {
-        plan_.run(n, stream, timing ? &timer_ : nullptr);
+        plan_.run(n, stream, timing ? &timer_ : nullptr, {sched()});
         HIPCHK(hipStreamSynchronize(stream));
         if (timing && n > 0) timer_.finish(n, stage_ms_);
         raise_status(take_status(), "");
@@ -778,6 +810,7 @@ public:
         const unsigned long long v = (unsigned long long)step;
         HIPCHK(hipMemcpyAsync(ctr_ + kStep, &v, sizeof v, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
+        sched_step_ = v;
     }
 
     void stage_ms(double *out) override { std::memcpy(out, stage_ms_, sizeof stage_ms_); }
@@ -789,6 +822,7 @@ public:
         HIPCHK(hipStreamSynchronize(stream));
         sort_state(tile_r, tile_th, sort_interval);
         fill(ctr_ + kNeedSort, 1, 1ull);
+        sched_need_ = true;
         plan_.build({rd_}, ppt_, stream);
         ++version;
     }
@@ -906,6 +940,8 @@ public:
         c[kCur] = 0;
         HIPCHK(hipMemcpyAsync(ctr_, c, sizeof c, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
+        sched_step_ = c[kStep];
+        sched_need_ = c[kNeedSort] != 0;
         qmax_ = h.qmax;
         if (set_dep_scale()) {
             plan_.upload({rd_}, stream);
@@ -924,7 +960,7 @@ public:
         unsigned long long c0[kNumCounters], c1[kNumCounters];
         read_counters(c0);
         HIPCHK(hipEventRecord(tev_[0], stream));
-        plan_.run(n, stream, nullptr);
+        plan_.run(n, stream, nullptr, {sched()});
         HIPCHK(hipEventRecord(tev_[1], stream));
         HIPCHK(hipStreamSynchronize(stream));
         raise_status(take_status(), "");
@@ -978,6 +1014,8 @@ private:
     unsigned int *counts_ = nullptr, *cursor_ = nullptr;
     unsigned long long *offsets_ = nullptr;
     int64_t cap_ = 0;
+    uint64_t sched_step_ = 0; // the device's kStep and kNeedSort, as every host action and step sets them
+    bool sched_need_ = true;
     double qmax_ = 0.0; // largest |w| held so far: sets the fixed-point deposit scale
     bool with_ids_ = false;
     Metric<T> m_{};
@@ -1182,7 +1220,9 @@ public:
         for (size_t r = 0; r < members_.size(); ++r) stale = stale || versions_[r] != members_[r]->version;
         if (stale) plan_.build(collect(), members_[0]->ppt(), stream_);
         HIPCHK(hipEventRecord(ev_[0], stream_));
-        plan_.run(n, stream_, timing ? &timer_ : nullptr);
+        std::vector<SortSched> sched;
+        for (EngineT<T> *m : members_) sched.push_back(m->sched());
+        plan_.run(n, stream_, timing ? &timer_ : nullptr, sched);
         HIPCHK(hipEventRecord(ev_[1], stream_));
         HIPCHK(hipStreamSynchronize(stream_));
         float ms = 0.f;

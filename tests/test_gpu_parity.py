@@ -167,6 +167,70 @@ def test_sort_groups_each_chunk_by_tile(prec):
     assert c["live"] + c["deleted"] == len(P["x"]) + c["injected"]
 
 
+def test_sorts_run_on_their_schedule():
+    """Only a sort changes the order in which the particles are stored: the
+    live particles keep their order through a step that does not sort, and
+    after one that does they are in the serpentine tile order of the cells
+    they held when the step began.  With a sort interval of 3, sorts come on
+    the first step and on every step whose index is a multiple of 3, also
+    after the step index is moved, and on the step after particles are added;
+    between them the launch sequence leaves the sort kernels out."""
+    from paper_1407_1810_amd.binding import Sim
+    cfg = W.small_config(nr=24, nth=16, pairs_per_cell=0, n_filt=1, absorb_cells=3, bg="monopole")
+    p = cfg["params"]
+    G, tr, tt = 2 * p["n_filt"] + 3, 2, 4
+    ntj = (p["nth"] + tt - 1) // tt
+    rng = np.random.default_rng(5)
+
+    def plasma(n, id0):
+        u = rng.normal(0.0, 1.0, (3, n))
+        u *= 2.0 / np.linalg.norm(u, axis=0)  # |u| = 2: 0.89 c
+        return dict(x=rng.uniform(0.5, p["nr"] - 0.5, n), y=rng.uniform(0.0, p["nth"], n), ur=u[0], ut=u[1],
+                    up=u[2], w=np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * cfg["weight"],
+                    id=np.arange(id0, id0 + n, dtype=np.uint64))
+
+    def keys(P):
+        i = np.floor(P["x"]).astype(np.int64)
+        j = np.minimum(np.floor(P["y"]).astype(np.int64), p["nth"] - 1)
+        ti, tj = (i + G) // tr, j // tt
+        tj = np.where(ti % 2 == 1, ntj - 1 - tj, tj)
+        return dict(zip(P["id"].tolist(), (ti * ntj + tj).tolist()))
+
+    P = plasma(3000, 0)
+    s = Sim(p, precision="fp64", capacity=10000, sort_interval=3, tile=(tr, tt))
+    s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+    reordered = 0
+
+    def one(step, sorts):
+        nonlocal reordered
+        before = s.particles()
+        k = keys(before)
+        s.step(1)
+        after = s.particles()["id"].tolist()
+        alive = set(after)
+        kept = [i for i in before["id"].tolist() if i in alive]
+        if sorts:
+            kk = [k[i] for i in after]
+            assert all(a <= b for a, b in zip(kk, kk[1:])), step
+            reordered += after != kept
+        else:
+            assert after == kept, step
+        assert s.counts()["step"] == step + 1
+
+    one(0, True)               # the first step sorts
+    for st in range(1, 9):
+        one(st, st % 3 == 0)
+    s.set_step_index(20)       # next sorts at steps 21 and 24
+    for st in range(20, 23):
+        one(st, st % 3 == 0)
+    Q = plasma(200, 5000)
+    s.add_particles(Q["x"], Q["y"], Q["ur"], Q["ut"], Q["up"], Q["w"], Q["id"])
+    one(23, True)              # sorts because particles arrived
+    for st in range(24, 28):
+        one(st, st % 3 == 0)
+    assert reordered >= 4
+
+
 @pytest.mark.parametrize("prec", PRECISIONS)
 def test_ten_steps_monopole_rotator_with_injection(prec):
     """Ten steps of a small monopole rotator: spin-up, surface injection
