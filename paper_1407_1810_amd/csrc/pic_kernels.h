@@ -10,7 +10,9 @@
 //
 //  k_step_begin ... particle-step count, sort decision, sort-span prefix
 //  k_sort_* ....... counting sort of particles by tile (serpentine order)
-//  k_zero_F ....... clear the deposit planes
+//  k_open ......... close the sorts, lay out the push chunks, clear the
+//                   deposit planes (and, on a step without the sort
+//                   kernels, the bookkeeping of k_step_begin)
 //  k_faraday ...... half Faraday update of B (App. A, eq. (discreteeq))
 //  k_push ......... gather + Vay/Boris push + move + VB deposit, one
 //                   work-group per chunk of cell-sorted particles, fields and
@@ -183,14 +185,12 @@ __global__ void k_fill(T *__restrict__ p, size_t n, T v)
 // ------------------------------------------------------------------
 
 // One thread: count the particle-steps this step advances, decide per run
-// whether it sorts (never when may_sort is 0: the launch sequence of a step
-// without the sort kernels), and lay the sort spans of the sorting runs end
-// to end.
+// whether it sorts (never when may_sort is 0: a step launched without the
+// sort kernels), and lay the sort spans of the sorting runs end to end.
 template <typename T>
-__global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int span,
-                             unsigned long long *__restrict__ span_off, int may_sort)
+__device__ void step_begin_one(const RunDev<T> *__restrict__ runs, int n_runs, int span,
+                               unsigned long long *__restrict__ span_off, int may_sort)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     unsigned long long acc = 0;
     for (int r = 0; r < n_runs; ++r) {
         const gptr<unsigned long long> c = glb(runs[r].ctr);
@@ -204,15 +204,21 @@ __global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int
     span_off[n_runs] = acc;
 }
 
+template <typename T>
+__global__ void k_step_begin(const RunDev<T> *__restrict__ runs, int n_runs, int span,
+                             unsigned long long *__restrict__ span_off, int may_sort)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) step_begin_one(runs, n_runs, span, span_off, may_sort);
+}
+
 // One thread: close the sort of every sorting run (the live count becomes
 // the particle count, deletions since the last sort join the total, the
 // buffers swap), then lay the push chunks of all runs end to end and reset
 // the per-XCD chunk counters.
 template <typename T>
-__global__ void k_sort_finish(const RunDev<T> *__restrict__ runs, int n_runs, int chunk,
-                              unsigned long long *__restrict__ chunk_off, unsigned int *__restrict__ work)
+__device__ void sort_finish_one(const RunDev<T> *__restrict__ runs, int n_runs, int chunk,
+                                unsigned long long *__restrict__ chunk_off, unsigned int *__restrict__ work)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     unsigned long long acc = 0;
     for (int r = 0; r < n_runs; ++r) {
         const gptr<unsigned long long> c = glb(runs[r].ctr);
@@ -235,12 +241,22 @@ __global__ void k_sort_finish(const RunDev<T> *__restrict__ runs, int n_runs, in
 // [off[r], off[r+1]) of the launch
 // ------------------------------------------------------------------
 
-// Clear the three deposit planes (256 threads x kZeroPerThread entries per
-// work-group).
+// The step's opening before the first Faraday half: work-group 0's first
+// thread does the bookkeeping (with begin set, that of a step launched
+// without the sort kernels: no run sorts; then the closing of the sorts and
+// the layout of the push chunks), and every work-group clears its share of
+// the three deposit planes (256 threads x kZeroPerThread entries each).
 template <typename T>
-__global__ __launch_bounds__(256) void k_zero_F(const RunDev<T> *__restrict__ runs, int n_runs,
-                                                const int *__restrict__ off)
+__global__ __launch_bounds__(256) void k_open(const RunDev<T> *__restrict__ runs, int n_runs,
+                                              const int *__restrict__ off, int begin, int span,
+                                              unsigned long long *__restrict__ span_off, int chunk,
+                                              unsigned long long *__restrict__ chunk_off,
+                                              unsigned int *__restrict__ work)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (begin) step_begin_one(runs, n_runs, span, span_off, 0);
+        sort_finish_one(runs, n_runs, chunk, chunk_off, work);
+    }
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];
     const size_t n = R.L.size();

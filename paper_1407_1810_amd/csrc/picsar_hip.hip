@@ -298,21 +298,21 @@ private:
     {
         const dim3 blk2(64, 4);
         mark(t, s, kStTotal, true);
+        // the sort stage is empty on a step without the sort kernels; the
+        // opening kernel then also does the step's bookkeeping
         mark(t, s, kStSort, true);
-        k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_, sort ? 1 : 0);
-        HIPCHK(hipGetLastError());
         if (sort) {
+            k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_, 1);
             if (tot_[kMapKeys] > 0) k_sort_zero<T><<<tot_[kMapKeys], 256, 0, s>>>(runs_, n_, map(kMapKeys));
             k_sort_hist<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
             k_sort_scan<T><<<n_, 1024, 0, s>>>(runs_);
             k_sort_scatter<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
             HIPCHK(hipGetLastError());
         }
-        k_sort_finish<T><<<1, 64, 0, s>>>(runs_, n_, 256 * ppt_, chunk_off_, work_);
-        HIPCHK(hipGetLastError());
         mark(t, s, kStSort, false);
         mark(t, s, kStZero, true);
-        k_zero_F<T><<<tot_[kMapZero], 256, 0, s>>>(runs_, n_, map(kMapZero));
+        k_open<T><<<tot_[kMapZero], 256, 0, s>>>(runs_, n_, map(kMapZero), sort ? 0 : 1, kSortSpan, span_off_,
+                                                 256 * ppt_, chunk_off_, work_);
         HIPCHK(hipGetLastError());
         mark(t, s, kStZero, false);
         mark(t, s, kStFaraday, true);
