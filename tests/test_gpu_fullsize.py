@@ -11,7 +11,9 @@ the FP64 oracle running the same step on the host cores:
   * the monopole rotator, 512 x 512, from an empty start: the first 30
     steps of surface injection (FP32 checked one step at a time, at steps
     10, 20 and 30);
-  * the four smallest runs of the 64-run ensemble, stepped as one batch.
+  * the four smallest runs of the 64-run ensemble, stepped as one batch;
+  * the 2048 x 2048 precision-stress workload (201M particles): FP64 three
+    steps, FP32 two steps one at a time (particles compared after the last).
 
 The per-step tolerances are those of the small parity tests (parity_util),
 FP32 fields measured against the scale of their vector field (E, B or F:
@@ -144,6 +146,38 @@ def test_dipole_rotator_1024_full_size(prec):
         sc = 1.0 if prec == "fp32" else (k + 1)
         compare_fields(o, s, _field_tol(prec, p) * 2 * sc, vector_scale=prec == "fp32")
         _compare_large(o, s, {kk: v * 2 * sc for kk, v in t.items()}, p["nth"], t["band"] * 2 * sc)
+    if prec == "fp64":
+        assert s.counts()["injected"] == o.counters()[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_precision_stress_2048_window(prec):
+    """The 2048 x 2048 precision-stress workload (48 particles per cell,
+    201M, injection on), whose long runs set the FP32 path beside the FP64
+    GPU path: both checked against the oracle over a short window, FP64 for
+    three steps run on, FP32 for two steps each from identical input bits."""
+    cfg = W.config(3)
+    p = cfg["params"]
+    t0 = time.time()
+    P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
+    n = len(P["x"])
+    _say(f"precision stress {prec}: {n} particles generated in {time.time() - t0:.1f} s")
+    o, s = _pair(p, P, prec, n + (8 << 20))
+    del P
+    t = TOL[prec]
+    steps = 3 if prec == "fp64" else 2
+    for k in range(steps):
+        if prec == "fp32" and k > 0:
+            o = oracle_from_sim(s, p)
+        t0 = time.time()
+        s.step(1)
+        t1 = time.time()
+        o.step(1)
+        _say(f" step {k}: gpu {t1 - t0:.2f} s, oracle {time.time() - t1:.1f} s, injected {o.counters()[0]}")
+        sc = 1.0 if prec == "fp32" else (k + 1)
+        compare_fields(o, s, _field_tol(prec, p) * 2 * sc, vector_scale=prec == "fp32")
+        if k == steps - 1:
+            _compare_large(o, s, {kk: v * 2 * sc for kk, v in t.items()}, p["nth"], t["band"] * 2 * sc)
     if prec == "fp64":
         assert s.counts()["injected"] == o.counters()[0]
 
