@@ -65,7 +65,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            raise RuntimeError(f"{LIB} is not built; run paper_1407_1810_amd/build.py (or __graft_entry__.build())")
+            raise RuntimeError(f"{LIB} is not built; run paper_1407_1810_amd/build.py")
         L = C.CDLL(LIB)
         P, d, i32, i64, u64, vp = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
         L.pic_create.argtypes = [P(vp), C.c_int, vp]

@@ -7,7 +7,7 @@ A particle-in-cell plasma is chaotic: two runs that differ only in the
 order of floating-point additions separate, and after enough steps their
 fields differ by the particle noise itself.  A second FP64 context with a
 different sort tile and interval (so a different order of the deposit's
-floating-point atomics) measures that floor; the FP32 path is judged
+floating-point atomics) measures that floor; the FP32 path is measured
 against it.
 
 On a geometric schedule of steps both FP64 contexts and the FP32 one are
