@@ -1340,12 +1340,13 @@ constexpr int kInjMaxPer = 8; // nth + 1 <= 8192
 template <typename T>
 __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ runs)
 {
-    __shared__ long long scan[1024];
+    __shared__ long long wsum[16];
     __shared__ int ok;
     const RunDev<T> &R = runs[blockIdx.x];
     const gptr<unsigned long long> ctr = glb(R.ctr);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t step = ctr[kStep];
+    const unsigned long long nbase = ctr[kTotal]; // fixed until this kernel's end
     if (!R.inject) {
         if (tid == 0) ctr[kStep] = step + 1;
         return;
@@ -1356,29 +1357,57 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
     const int nth = L.nth, nodes = nth + 1;
     const int per = (nodes + 1023) / 1024;
     const int j0 = tid * per, j1 = min(j0 + per, nodes);
+    // every input of this thread's nodes is loaded (at a node clamped into
+    // the tables) before the first carry is stored
+    double er[kInjMaxPer], kn[kInjMaxPer], sn[kInjMaxPer], cy[kInjMaxPer], aj[kInjMaxPer];
+#pragma unroll
+    for (int q = 0; q < kInjMaxPer; ++q) {
+        if (q < per) {
+            const int jj = min(j0 + q, nodes - 1);
+            er[q] = (double)glb(R.fld[cER])[L.at(0, jj)];
+            kn[q] = glb(R.kn)[jj];
+            sn[q] = glb(R.sn)[jj];
+            cy[q] = glb(R.carry)[jj];
+            aj[q] = glb(R.Aj)[jj];
+        }
+    }
     long long m[kInjMaxPer];
     long long mine = 0;
-    for (int jj = j0; jj < j1; ++jj) {
-        double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-        add_background(R.bg, irl, false, R.rb0, glb(R.kn)[jj], glb(R.sn)[jj], E, B);
-        const double sigma = (double)glb(R.fld[cER])[L.at(0, jj)] + E[0];
-        const double cnew = glb(R.carry)[jj] + R.f_inj * fabs(sigma) * glb(R.Aj)[jj] / R.q_inj;
-        const double fl = floor(cnew);
-        glb(R.carry)[jj] = cnew - fl;
-        m[jj - j0] = (long long)fl;
-        mine += (long long)fl;
+#pragma unroll
+    for (int q = 0; q < kInjMaxPer; ++q) {
+        m[q] = 0;
+        const int jj = j0 + q;
+        if (q < per && jj < j1) {
+            double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+            add_background(R.bg, irl, false, R.rb0, kn[q], sn[q], E, B);
+            const double sigma = er[q] + E[0];
+            const double cnew = cy[q] + R.f_inj * fabs(sigma) * aj[q] / R.q_inj;
+            const double fl = floor(cnew);
+            glb(R.carry)[jj] = cnew - fl;
+            m[q] = (long long)fl;
+            mine += (long long)fl;
+        }
     }
-    scan[tid] = mine;
+    // exclusive prefix of the counts over the threads: within each wave by
+    // shuffles, then over the sixteen wave totals
+    long long incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const long long v = tid >= o ? scan[tid - o] : 0;
-        __syncthreads();
-        scan[tid] += v;
-        __syncthreads();
+    if (wv == 0) {
+        long long w = lane < 16 ? wsum[lane] : 0;
+        for (int o = 1; o < 16; o <<= 1) {
+            const long long v = __shfl_up(w, o);
+            if (lane >= o) w += v;
+        }
+        if (lane < 16) wsum[lane] = w;
     }
-    const long long total = scan[1023];
-    long long off = scan[tid] - mine;
-    const unsigned long long nbase = ctr[kTotal];
+    __syncthreads();
+    const long long total = wsum[15];
+    long long off = (wv > 0 ? wsum[wv - 1] : 0) + incl - mine;
     if (tid == 0) ok = (long long)nbase + 2 * total <= R.capacity;
     __syncthreads();
     if (!ok) {
@@ -1392,10 +1421,13 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
     const gptr<T> a[6] = {glb(R.arr[cur][0]), glb(R.arr[cur][1]), glb(R.arr[cur][2]),
                           glb(R.arr[cur][3]), glb(R.arr[cur][4]), glb(R.arr[cur][5])};
     const gptr<uint64_t> id = R.id[cur] ? glb(R.id[cur]) : nullptr;
-    for (int jj = j0; jj < j1; ++jj) {
+#pragma unroll
+    for (int q = 0; q < kInjMaxPer; ++q) {
+        const int jj = j0 + q;
+        if (!(q < per && jj < j1)) continue;
         const double ylo = jj - 0.5 < 0.0 ? 0.0 : jj - 0.5;
         const double yhi = jj + 0.5 > nth ? (double)nth : jj + 0.5;
-        for (long long kk = 0; kk < m[jj - j0]; ++kk) {
+        for (long long kk = 0; kk < m[q]; ++kk) {
             uint64_t x[4] = {step, (uint64_t)jj, (uint64_t)kk, 0};
             philox4x64(x, R.seed, 0x50494353ull);
             const double U = (double)(x[0] >> 11) * 0x1.0p-53;
@@ -1415,7 +1447,7 @@ __global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ r
                             (uint64_t)sgn;
             }
         }
-        off += m[jj - j0];
+        off += m[q];
     }
     __syncthreads();
     if (tid == 0) {
