@@ -719,15 +719,11 @@ struct LdsView {
     const T *rn; // r(i) of the region's rows at [i - i0]
     int i0, j0, C;
     __device__ T r_node(int i) const { return rn[i - i0]; }
-    // The four values of lattice plane c around entry e, interpolated.
-    __device__ T bilin_at(int c, int e, T x, T y) const
-    {
-        const T *a = s + c * P + e;
-        return bilin(a[0], a[C], a[1], a[C + 1], x, y);
-    }
     // As GlobalView::gather; the axis mirror was applied when the planes
     // were staged, and the stencils of the four lattices are reached from
-    // one entry by steps of one row (C) or one column.
+    // one entry by steps of one row (C) or one column.  All 24 values are
+    // read before the first is used, so that the particle waits for LDS
+    // once rather than once per component.
     __device__ void gather(int i, int j, T fx, T fy, T E[3], T B[3]) const
     {
         const int e = lds_entry(i, j, i0, j0, C);
@@ -736,12 +732,23 @@ struct LdsView {
         if (hx < (T)0) { ex = e - C; hx += (T)1; }
         if (hy < (T)0) { ey = e - 1; hy += (T)1; }
         const int exy = ex + (ey - e);
-        E[0] = bilin_at(cER, ex, hx, fy);
-        E[1] = bilin_at(cETH, ey, fx, hy);
-        E[2] = bilin_at(cEPH, e, fx, fy);
-        B[0] = bilin_at(cBR, ey, fx, hy);
-        B[1] = bilin_at(cBTH, ex, hx, fy);
-        B[2] = bilin_at(cBPH, exy, hx, hy);
+        const int at[6] = {ex, ey, e, ey, ex, exy};
+        const int comp[6] = {cER, cETH, cEPH, cBR, cBTH, cBPH};
+        T v[6][4];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const T *a = s + comp[q] * P + at[q];
+            v[q][0] = a[0];
+            v[q][1] = a[C];
+            v[q][2] = a[1];
+            v[q][3] = a[C + 1];
+        }
+        E[0] = bilin(v[0][0], v[0][1], v[0][2], v[0][3], hx, fy);
+        E[1] = bilin(v[1][0], v[1][1], v[1][2], v[1][3], fx, hy);
+        E[2] = bilin(v[2][0], v[2][1], v[2][2], v[2][3], fx, fy);
+        B[0] = bilin(v[3][0], v[3][1], v[3][2], v[3][3], fx, hy);
+        B[1] = bilin(v[4][0], v[4][1], v[4][2], v[4][3], hx, fy);
+        B[2] = bilin(v[5][0], v[5][1], v[5][2], v[5][3], hx, hy);
     }
 };
 
