@@ -74,6 +74,49 @@ def test_batch_matches_the_oracle_run_by_run(prec):
     b.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_with_empty_runs_and_offset_steps(prec):
+    """A batch holding a filled run, an empty run that fills by surface
+    injection and starts at step index 7 (its sorts, every 3 steps, fall on
+    other steps than the first run's, every 2), and an empty run without
+    injection (nothing to push or sort at all): each run against its own
+    oracle after every step."""
+    from paper_1407_1810_amd.binding import Batch
+    specs = [
+        (dict(nr=24, nth=20, pairs_per_cell=2, n_filt=2, absorb_cells=4, bg="monopole", omega_frac=0.3, inject=1,
+              seed=21), True, 2, 0),
+        (dict(nr=28, nth=24, pairs_per_cell=0, n_filt=3, absorb_cells=4, bg="monopole", omega_frac=0.3, inject=1,
+              seed=22), False, 3, 7),
+        (dict(nr=20, nth=16, pairs_per_cell=0, n_filt=1, absorb_cells=3, bg="dipole", omega_frac=0.2, inject=0,
+              seed=23), False, 4, 0),
+    ]
+    runs = []
+    for sp, filled, si, step0 in specs:
+        cfg = W.small_config(**sp)
+        p = dict(cfg["params"], q_inj=cfg["params"]["q_inj"] * 0.5, t_spin=3.0)
+        P = None
+        if filled:
+            P = W.pair_plasma(p, cfg["pairs_per_cell"], 0.2, cfg["weight"], sp["seed"])
+            P["x"][1::4] = np.clip(P["x"][1::4] + 0.37, 0.0, p["nr"] - 1e-9)
+        o, s = make_pair(p, P, prec, capacity=1 << 18, tile=(4, 4), sort_interval=si, step_index=step0)
+        runs.append((p, o, s, step0))
+    b = Batch([s for _, _, s, _ in runs])
+    t = TOL[prec]
+    for k in range(7):
+        b.step(1)
+        for p, o, s, step0 in runs:
+            o.step(1)
+            scale = 10.0 * (1.0 if prec == "fp32" else (k + 1))
+            compare_fields(o, s, t["field"] * scale)
+            compare_particles(o, s, {kk: v * scale for kk, v in t.items()}, p["nth"], t["band"] * scale)
+            assert s.counts()["step"] == step0 + k + 1
+    assert runs[1][2].counts()["injected"] > 0
+    assert runs[2][2].counts()["live"] == 0
+    for _, o, s, _ in runs:
+        assert s.counts()["injected"] == o.counters()[0]
+    b.close()
+
+
 def test_graph_and_eager_steps_agree():
     """pic_step replays a captured graph; with stage timing on it enqueues
     the same launches one by one.  Both give the same state."""
