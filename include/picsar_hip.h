@@ -42,8 +42,9 @@
  *  - pic_step() enqueues on the context's stream and synchronises before it
  *    returns, so that device-side errors (CFL, capacity) are reported by
  *    the call that caused them.  Without stage timing the launches of one
- *    step are captured once into a HIP graph and replayed; with timing on
- *    they are enqueued one by one between HIP events.
+ *    step are captured into HIP graphs, one with the particle sort and one
+ *    without (used on steps where no run is due to sort), and replayed;
+ *    with timing on they are enqueued one by one between HIP events.
  */
 #ifndef PICSAR_HIP_H
 #define PICSAR_HIP_H
