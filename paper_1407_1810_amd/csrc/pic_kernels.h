@@ -1010,9 +1010,10 @@ __device__ inline POut<T> push_particle(const PushArgs<T> &p, const V &view, con
         s = sin(th);
         k = -cos(th);
     }
-    const T u0 = in.u0, u1 = in.u1, u2 = in.u2;
-    // Cartesian frame at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = (0, 1, 0)
-    T uc[3] = {s * u0 + k * u1, u2, k * u0 - s * u1};
+    // the momentum in the local basis (e_r, e_th, e_ph) at the start point;
+    // the movers are vector operations, the same in any orthonormal basis,
+    // so they work there on the local E and B as gathered
+    T ul[3] = {in.u0, in.u1, in.u2};
     const bool outer = i > nr || (i == nr && fx > (T)0); // beyond the outer conductor: ballistic
     const bool inner = i < 0;                            // inside the star: corotation field only
     const T eps = w > (T)0 ? p.eps0 : (w < (T)0 ? -p.eps0 : (T)0);
@@ -1025,17 +1026,17 @@ __device__ inline POut<T> push_particle(const PushArgs<T> &p, const V &view, con
             E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = (T)0;
         }
         add_background(p.bg, p.inv_rl, inner, r, ir, k, s, E, B);
-        const T Ec[3] = {s * E[0] + k * E[1], E[2], k * E[0] - s * E[1]};
-        const T Bc[3] = {s * B[0] + k * B[1], B[2], k * B[0] - s * B[1]};
         if (p.mover == 0) {
-            ig = vay_push(uc, Ec, Bc, eps);
+            ig = vay_push(ul, E, B, eps);
         } else {
-            boris_push(uc, Ec, Bc, eps);
-            ig = FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+            boris_push(ul, E, B, eps);
+            ig = FM<T>::rsqrt((T)1 + ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2]);
         }
     } else {
-        ig = FM<T>::rsqrt((T)1 + uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+        ig = FM<T>::rsqrt((T)1 + ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2]);
     }
+    // Cartesian frame at phi = 0: e_r = (s, 0, k), e_th = (k, 0, -s), e_ph = (0, 1, 0)
+    const T uc[3] = {s * ul[0] + k * ul[1], ul[2], k * ul[0] - s * ul[1]};
     // displacement over the step, relative to r
     const T vg = p.c * ig;
     const T ex = uc[0] * vg * ir, ey = uc[1] * vg * ir, ez = uc[2] * vg * ir;
