@@ -76,6 +76,29 @@ def test_one_step_with_particles(prec, nf):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("r_kind,th_kind,mover,bg", [("lin", "lin", "boris", "dipole"), ("log", "lin", "vay", "dipole"),
+                                                     ("lin", "eqarea", "boris", "monopole")])
+def test_one_step_other_grids_and_boris(prec, r_kind, th_kind, mover, bg):
+    """One full step as above on the other mesh options of Sec. 3.2 (uniform
+    radius, uniform angle) and with the Boris mover: the push's radius,
+    angle and displacement formulas for each option, both hemispheres of
+    the uniform-angle mesh, and the second mover."""
+    cfg, P = _small(nr=36, nth=40, pairs_per_cell=4, n_filt=2, absorb_cells=5, theta_T=0.3, r_kind=r_kind,
+                    th_kind=th_kind, mover=mover, bg=bg)
+    p = cfg["params"]
+    P["x"][1::4] = np.clip(P["x"][1::4] + 0.41, 0.0, p["nr"] - 1e-9)
+    _say("one-step-grid", prec, r_kind, th_kind, mover, bg, len(P["x"]))
+    from oracle.oracle import Oracle
+    flds = random_fields(Oracle(p), np.random.default_rng(5), scale=3e-3)
+    o, s = make_pair(p, P, prec, fields=flds)
+    o.step(1)
+    s.step(1)
+    t = TOL[prec]
+    compare_fields(o, s, t["field"])
+    compare_particles(o, s, t, p["nth"], t["band"])
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_lds_and_global_paths_and_sort(prec):
     """Same result with the chunk staged in LDS (after a sort) and with the
     global-memory path (no sort: chunks of scattered particles)."""
