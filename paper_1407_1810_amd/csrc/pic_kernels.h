@@ -468,6 +468,7 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     constexpr int NR = kFiltTR + 2 * H, NC = kFiltTC + 2 * H, N = NR * NC;
     constexpr int KN = (N + 255) / 256, KO = kFiltTR * kFiltTC / 256; // entries per thread: tile + halo, tile
     static_assert(kFiltTR * kFiltTC % 256 == 0, "the filter tile is a whole number of 256-entry sweeps");
+    static_assert(3 * N * sizeof(T) <= 65536, "the filter's LDS arrays fit in 64 KB");
     __shared__ T sa[N], sb[N], st[N];
     const int r = run_of(off, n_runs, blockIdx.x);
     const RunDev<T> &R = runs[r];

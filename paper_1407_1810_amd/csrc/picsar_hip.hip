@@ -331,6 +331,7 @@ private:
         if (tot_[kMapFilter] > 0) {
             const dim3 fg(tot_[kMapFilter], 3);
             if (max_filt_ <= 2) k_filter<T, 2><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
+            else if (max_filt_ == 3) k_filter<T, 3><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
             else if (max_filt_ <= 4) k_filter<T, 4><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
             else k_filter<T, 8><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
             HIPCHK(hipGetLastError());

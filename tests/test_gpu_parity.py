@@ -58,7 +58,7 @@ def test_fields_only_one_and_five_steps(prec):
 def test_one_step_with_particles(prec, nf):
     """One full step from identical inputs: fields (E, B and the filtered
     face charges) and every particle, matched by id.  The pass counts reach
-    every halo width the filter kernel is built for (2, 4 and 8), up to the
+    every halo width the filter kernel is built for (2, 3, 4 and 8), up to the
     largest count the library accepts."""
     cfg, P = _small(nr=40, nth=36, pairs_per_cell=4, n_filt=nf, absorb_cells=5, theta_T=0.3)
     p = cfg["params"]
