@@ -136,8 +136,31 @@ struct FM<double> {
         is = 1.0 / s;
     }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
-    static __device__ __forceinline__ double log1p(double e) { return ::log1p(e); }
-    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    // log(1 + e): alternating series through e^12 for |e| < 1/32 (truncation
+    // below e^13 / 13 < 2^-63 |e|, under FP64 rounding), else the library
+    static __device__ __forceinline__ double log1p(double e)
+    {
+        if (fabs(e) < 0.03125) {
+            double v = 1.0 / 12;
+#pragma unroll
+            for (int k = 11; k >= 2; --k) v = 1.0 / k - e * v;
+            return e - e * e * v;
+        }
+        return ::log1p(e);
+    }
+    // atan2(y, x) for x > 0 and |y| < x / 8: odd series of atan(y / x)
+    // through t^17 (truncation < t^19 / 19 < 2^-58 |t|), else the library
+    static __device__ __forceinline__ double atan2(double y, double x)
+    {
+        if (x > 0.0 && fabs(y) < 0.125 * x) {
+            const double t = y / x, t2 = t * t;
+            double v = 1.0 / 17;
+#pragma unroll
+            for (int m = 7; m >= 1; --m) v = 1.0 / (2 * m + 1) - t2 * v;
+            return t - t * t2 * v;
+        }
+        return ::atan2(y, x);
+    }
 };
 
 // Analytic initial ("vacuum") field of the rotating conductor, Sec. 5.2 and
