@@ -86,6 +86,7 @@ struct FM<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     // sqrt(x) and 1/sqrt(x) of x > 0 from one hardware reciprocal square root
     static __device__ __forceinline__ void sqrt_rsqrt(float x, float &s, float &is)
@@ -144,6 +145,12 @@ struct FM<double> {
     }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); } // x = 0 occurs (the poles)
     static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
+    // sqrt(x) of normal x > 0: x / sqrt(x) with one correction from its residual
+    static __device__ __forceinline__ double sqrt_pos(double x)
+    {
+        const double is = rsqrt(x), s0 = x * is;
+        return fma(fma(-s0, s0, x), 0.5 * is, s0);
+    }
     // sqrt(x) and 1/sqrt(x) of normal x > 0; the square root takes one
     // correction from its residual
     static __device__ __forceinline__ void sqrt_rsqrt(double x, double &s, double &is)
@@ -152,7 +159,22 @@ struct FM<double> {
         const double s0 = x * is;
         s = fma(fma(-s0, s0, x), 0.5 * is, s0);
     }
-    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    // exp(x): Taylor series through x^8 for |x| < 1/32 (truncation below
+    // x^9 / 9! < 2^-63), else the library
+    static __device__ __forceinline__ double exp(double x)
+    {
+        if (fabs(x) < 0.03125) {
+            double v = fma(x, 1.0 / 40320, 1.0 / 5040); // 1/8!, 1/7!
+            v = fma(x, v, 1.0 / 720);
+            v = fma(x, v, 1.0 / 120);
+            v = fma(x, v, 1.0 / 24);
+            v = fma(x, v, 1.0 / 6);
+            v = fma(x, v, 0.5);
+            v = fma(x, v, 1.0);
+            return fma(x, v, 1.0);
+        }
+        return ::exp(x);
+    }
     // log(1 + e): alternating series through e^12 for |e| < 1/32 (truncation
     // below e^13 / 13 < 2^-63 |e|, under FP64 rounding), else the library
     static __device__ __forceinline__ double log1p(double e)
@@ -262,7 +284,7 @@ __device__ inline T vay_push(T u[3], const T E[3], const T B[3], T eps)
     const T tau2 = tx * tx + ty * ty + tz * tz;
     const T us = px * tx + py * ty + pz * tz;
     const T sg = (T)1 + px * px + py * py + pz * pz - tau2;
-    const T g2 = (T)0.5 * (sg + FM<T>::sqrt(sg * sg + (T)4 * (tau2 + us * us)));
+    const T g2 = (T)0.5 * (sg + FM<T>::sqrt_pos(sg * sg + (T)4 * (tau2 + us * us))); // > 0: sg >= 1 where tau = 0
     const T ign = FM<T>::rsqrt(g2);
     const T ax = tx * ign, ay = ty * ign, az = tz * ign;
     const T sf = FM<T>::rcp((T)1 + ax * ax + ay * ay + az * az);
