@@ -75,8 +75,10 @@ struct GFields {
 // square root (1 ulp), exp via v_exp_f32, and short series for the small
 // arguments the push sees (log1p of r'/r - 1, atan of the azimuthal step),
 // falling back to the library outside their range; all far inside the FP32
-// parity tolerance.  FP64: IEEE division / square root and the library
-// functions, for parity at 1e-12 with the FP64 oracle.
+// parity tolerance.  FP64: the hardware reciprocal estimates refined by
+// Newton steps, IEEE square root where the argument can be zero, and series
+// of the same kind with more terms (exp, log1p, atan), each within an ulp of
+// the exact value, so that parity with the FP64 oracle holds at 1e-12.
 // ---------------------------------------------------------------------
 template <typename T>
 struct FM;
