@@ -113,6 +113,15 @@ def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt):
                deleted=c1["deleted"])
     log(f"[{precision}] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
         f"stages {json.dumps({k: round(v, 4) for k, v in st.items()})}")
+    # the Gauss-law residual (an occasional diagnostic, outside the timed
+    # steps): one whole call, with its allocations, the node charge, its
+    # filter passes, the FP64 flux kernel and the copy of both arrays to the
+    # host; the second of two calls
+    for _ in range(2):
+        t0 = time.perf_counter()
+        s.gauss()
+        res["gauss_diagnostic_ms"] = 1e3 * (time.perf_counter() - t0)
+    log(f"[{precision}] Gauss residual diagnostic: {res['gauss_diagnostic_ms']:.2f} ms per call")
     s.close()
     return res
 
@@ -354,7 +363,8 @@ def main():
         "fp64_gpu": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
             "stage_ms": {k: round(v, 5) for k, v in r64["stage_ms"].items()},
-            "fp32_speedup": r32["value"] / r64["value"]},
+            "fp32_speedup": r32["value"] / r64["value"], "gauss_diagnostic_ms": r64["gauss_diagnostic_ms"]},
+        "gauss_diagnostic_ms": r32["gauss_diagnostic_ms"],
         "batched_fp32": rb,
         "cpu_baseline": cpu,
     }
