@@ -1761,22 +1761,85 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ src, co
 // Gauss diagnostic in FP64
 // ------------------------------------------------------------------
 
+// Node charge of the particles, bilinear at the four nodes of each cell.
+// A work-group takes kNodeSpan consecutive particle slots.  When the nodes
+// they reach fit in kNodeLds LDS entries (cell-sorted particles), the
+// charges are summed there with LDS atomics and each node the span reaches
+// is flushed with one global atomic; otherwise every contribution goes to
+// global memory.  The grid covers the store's capacity; work-groups past
+// the particle count return at once.
+constexpr int kNodeSpan = 4096, kNodeLds = 4096;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict__ cell, const T *__restrict__ dx,
                                                      const T *__restrict__ dy, const T *__restrict__ w,
                                                      const unsigned long long *n_total, Layout L, double *rho)
 {
+    __shared__ double acc[kNodeLds];
+    __shared__ int red[4][4];
     const unsigned long long n = *n_total;
-    for (unsigned long long q = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; q < n;
-         q += (unsigned long long)gridDim.x * blockDim.x) {
-        const uint32_t c = cell[q];
+    const unsigned long long base = (unsigned long long)blockIdx.x * kNodeSpan;
+    if (base >= n) return; // the same for the whole work-group
+    const int cnt = (int)min((unsigned long long)kNodeSpan, n - base);
+    const int tid = threadIdx.x, wv = tid >> 6;
+    // cell bounding box of the span's live particles
+    int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+    for (int k = tid; k < cnt; k += 256) {
+        const uint32_t c = cell[base + k];
         if (c == kDead) continue;
         const int i = cell_i(c), j = cell_j(c);
-        const double fx = dx[q], fy = dy[q], Q = w[q];
-        unsafeAtomicAdd(&rho[L.at(i, j)], Q * (1 - fx) * (1 - fy));
-        unsafeAtomicAdd(&rho[L.at(i + 1, j)], Q * fx * (1 - fy));
-        unsafeAtomicAdd(&rho[L.at(i, j + 1)], Q * (1 - fx) * fy);
-        unsafeAtomicAdd(&rho[L.at(i + 1, j + 1)], Q * fx * fy);
+        imin = min(imin, i);
+        imax = max(imax, i);
+        jmin = min(jmin, j);
+        jmax = max(jmax, j);
+    }
+    imin = wave_min(imin);
+    imax = wave_max(imax);
+    jmin = wave_min(jmin);
+    jmax = wave_max(jmax);
+    if ((tid & 63) == 0) {
+        red[wv][0] = imin;
+        red[wv][1] = imax;
+        red[wv][2] = jmin;
+        red[wv][3] = jmax;
+    }
+    __syncthreads();
+    imin = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+    imax = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1]));
+    jmin = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+    jmax = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
+    if (imin > imax) return; // no live particle in the span (the same for the whole work-group)
+    const long long W = (long long)(jmax - jmin) + 2, NH = (long long)(imax - imin) + 2;
+    if (W * NH <= kNodeLds) {
+        const int nw = (int)W, ne = (int)(W * NH);
+        for (int e = tid; e < ne; e += 256) acc[e] = 0.0;
+        __syncthreads();
+        for (int k = tid; k < cnt; k += 256) {
+            const uint32_t c = cell[base + k];
+            if (c == kDead) continue;
+            const int e = (cell_i(c) - imin) * nw + (cell_j(c) - jmin); // node (i, j); (i + 1, j) is e + nw
+            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k];
+            atomicAdd(&acc[e], Q * (1 - fx) * (1 - fy));
+            atomicAdd(&acc[e + nw], Q * fx * (1 - fy));
+            atomicAdd(&acc[e + 1], Q * (1 - fx) * fy);
+            atomicAdd(&acc[e + nw + 1], Q * fx * fy);
+        }
+        __syncthreads();
+        for (int e = tid; e < ne; e += 256) {
+            const double v = acc[e];
+            if (v != 0.0) unsafeAtomicAdd(&rho[L.at(imin + e / nw, jmin + e % nw)], v);
+        }
+    } else {
+        for (int k = tid; k < cnt; k += 256) {
+            const uint32_t c = cell[base + k];
+            if (c == kDead) continue;
+            const int i = cell_i(c), j = cell_j(c);
+            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k];
+            unsafeAtomicAdd(&rho[L.at(i, j)], Q * (1 - fx) * (1 - fy));
+            unsafeAtomicAdd(&rho[L.at(i + 1, j)], Q * fx * (1 - fy));
+            unsafeAtomicAdd(&rho[L.at(i, j + 1)], Q * (1 - fx) * fy);
+            unsafeAtomicAdd(&rho[L.at(i + 1, j + 1)], Q * fx * fy);
+        }
     }
 }
 

@@ -742,8 +742,9 @@ public:
             G = dev_alloc<double>(N);
             fill(rho, fsz, 0.0);
             fill(tmp, fsz, 0.0);
-            k_node_charge<T><<<2048, 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1], arr_[cur][5],
-                                                       ctr_ + kTotal, L, rho);
+            const int spans = (int)((cap_ + kNodeSpan - 1) / kNodeSpan);
+            k_node_charge<T><<<std::max(spans, 1), 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1],
+                                                                    arr_[cur][5], ctr_ + kTotal, L, rho);
             HIPCHK(hipGetLastError());
             double *a = rho, *b = tmp;
             const dim3 blk(64, 4), fg((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4);
