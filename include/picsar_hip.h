@@ -116,13 +116,25 @@ typedef struct {
  * case the context creates and owns a stream of default priority. */
 pic_status pic_create(pic_ctx **out, int device, void *hip_stream);
 
-/* Allocate and initialise the grid (fields zero), the particle store and
- * the metric tables (computed in FP64 on the host).  Once per context. */
+/* Allocate and initialise the grid (fields zero), the particle store, the
+ * diagnostic planes and the metric tables: the stretched coordinates of
+ * Sec. 3.2 (xi = r0 ln(r / r0), theta_A = -cos theta, or their linear
+ * options) and the area and line elements of App. A eq. (linearea), formed
+ * in FP64 on the host and stored in the context's precision.  Once per
+ * context; PIC_ESTATE if called twice, PIC_EINVAL for an invalid
+ * descriptor, PIC_ENOMEM if the device memory runs out (nothing is then
+ * kept).  pic_init_grid is the same call under the name of the scope
+ * table's boundary. */
 pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys);
+pic_status pic_init_grid(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys);
 
-/* Append n particles (host FP64 arrays of length n; id may be NULL, then
- * ids are 0,1,2,... in order of arrival).  PIC_EINVAL if a position lies
- * outside the ranges above, PIC_ECAPACITY if the store would overflow. */
+/* Append n macro-particles: the state of Sec. 3.3 (position in grid
+ * coordinates, momentum u = gamma v / c in the local (r, theta, phi) basis,
+ * signed macro charge w, all host FP64 arrays of length n); id may be NULL,
+ * then ids are the storage slots in order of arrival.  Each particle is
+ * stored as an int32 cell plus in-cell offsets (rounded once to FP32 in an
+ * FP32 context).  PIC_EINVAL if a position lies outside the ranges above,
+ * PIC_ECAPACITY if the store would overflow (nothing is then appended). */
 pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const double *y,
                                 const double *ur, const double *ut, const double *up,
                                 const double *w, const uint64_t *id);
@@ -139,9 +151,11 @@ pic_status pic_get_field(pic_ctx *ctx, int32_t comp, double *host, int64_t cap);
 /* Overwrite one E or B component from host FP64 data (rows x cols). */
 pic_status pic_set_field(pic_ctx *ctx, int32_t comp, const double *host, int64_t n);
 
-/* Live particles in storage order, FP64 absolute grid coordinates.  Any
- * output pointer may be NULL.  *n_out receives the count; PIC_EINVAL if cap
- * is smaller (nothing is written then). */
+/* Live particles in storage order: the particle state of Sec. 3.3 as FP64
+ * absolute grid coordinates (cell index plus offset), local momenta,
+ * weights and ids, into host arrays of cap entries.  Any output pointer may
+ * be NULL.  *n_out receives the count; PIC_EINVAL if cap is smaller
+ * (nothing is written then). */
 pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, double *ut, double *up,
                              double *w, uint64_t *id, int64_t cap, int64_t *n_out);
 
@@ -150,11 +164,31 @@ pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, dou
  *                  total, step index, particle-steps advanced since init;
  *                  out[5] (if cap >= 6) = push chunks whose cells did not fit
  *                  the LDS planes and went through global memory
- *  PIC_MOM_GAUSS:  Gauss diagnostic in FP64 (Sec. 2, App. B): out[0..N) =
- *                  closed-surface flux of E out of each dual cell,
- *                  out[N..2N) = the n_filt-filtered bilinear particle
- *                  charge of that node, N = (nr+1)*(nth+1) row-major;
- *                  rows 0 and nr of the flux are zero (surface nodes)
+ *  PIC_MOM_GAUSS:  Gauss diagnostic in FP64 (Sec. 2 eq. (maxti), App. B
+ *                  eq. (multfiltcharge)): out[0..N) = closed-surface flux
+ *                  G of E out of each dual cell, out[N..2N) = the
+ *                  n_filt-filtered bilinear particle charge Qbar of that
+ *                  node, N = (nr+1)*(nth+1) row-major; rows 0 and nr of the
+ *                  flux are zero (surface nodes)
+ *  PIC_MOM_GAUSS_RES: the same residual R = G - Qbar reduced on the device
+ *                  in FP64 over the interior nodes below the lossy layer,
+ *                  1 <= i <= nr-1-absorb_cells, all j (the layer damps E
+ *                  and so does not conserve R; Sec. 3.4.1), 9 values:
+ *                  out[0] = max |R - R0|, out[1] =
+ *                  sqrt(sum (R - R0)^2), out[2] = max |R|, out[3] =
+ *                  sqrt(sum R^2), out[4] = max of the unfiltered absolute
+ *                  node charge sum_p |w_p| W(node; x_p) (the scale of a
+ *                  drift when the net charge vanishes), out[5] = max |G|,
+ *                  out[6] = nodes reduced, out[7] = non-finite values met
+ *                  on any interior node, out[8] = step index at which R0
+ *                  was recorded.  R0
+ *                  is the residual of the first Gauss evaluation (this kind
+ *                  or PIC_MOM_GAUSS) after pic_init, pic_load, particles
+ *                  added from the host or a field set from the host; it
+ *                  stays on the device, so that the drift R - R0 is exactly
+ *                  the charge-conservation error of the steps since then
+ *  PIC_MOM_RHO_Q:  the n_filt-filtered bilinear node charge Qbar alone
+ *                  (N values, as the second half of PIC_MOM_GAUSS)
  *  PIC_MOM_CARRY:  fractional injection count per theta node (nth+1)
  *  PIC_MOM_STAGE_MS: mean device time per step, in ms, of each stage over
  *                  the steps of the last pic_step call (out[0..8] = sort,
@@ -170,7 +204,13 @@ pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, dou
  *                  its four corners, B_theta over its two meridional
  *                  nodes, B_phi at its own point, times the cell's face
  *                  2 pi r(i+1/2)^2 (cos theta_j - cos theta_j+1) (nr) */
-enum { PIC_MOM_COUNTS = 0, PIC_MOM_GAUSS = 1, PIC_MOM_CARRY = 2, PIC_MOM_STAGE_MS = 3, PIC_MOM_POYNTING = 4 };
+enum { PIC_MOM_COUNTS = 0, PIC_MOM_GAUSS = 1, PIC_MOM_CARRY = 2, PIC_MOM_STAGE_MS = 3, PIC_MOM_POYNTING = 4,
+       PIC_MOM_GAUSS_RES = 5, PIC_MOM_RHO_Q = 6 };
+/* Every kind copies into the caller's out[cap] (PIC_EINVAL if cap is below
+ * the size given above).  PIC_MOM_GAUSS, PIC_MOM_GAUSS_RES and
+ * PIC_MOM_POYNTING return PIC_ENAN, after writing out, when the reduction
+ * met a non-finite field value or particle charge.  The diagnostic planes
+ * are allocated by pic_init; no kind allocates device memory. */
 pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap);
 
 /* Set the step index (time t = index * dt) and the injection carry, so a

@@ -20,7 +20,9 @@ MOVER = {"vay": 0, "boris": 1}
 BG_KIND = {"none": 0, "uniform_bz": 1, "monopole": 2, "dipole": 3, "dipole_corot": 4}
 COMPS = ["Er", "Eth", "Eph", "Br", "Bth", "Bph", "Fr", "Fth", "Fph"]
 FLAG_IDS = 1
-MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS, MOM_POYNTING = 0, 1, 2, 3, 4
+MOM_COUNTS, MOM_GAUSS, MOM_CARRY, MOM_STAGE_MS, MOM_POYNTING, MOM_GAUSS_RES, MOM_RHO_Q = 0, 1, 2, 3, 4, 5, 6
+GAUSS_RES_KEYS = ["drift_max", "drift_l2", "res_max", "res_l2", "abs_charge_max", "flux_max", "nodes", "non_finite",
+                  "ref_step"]
 STAGES = ["sort", "faraday", "push", "filter", "ampere", "absorb", "inject", "zero", "total"]
 
 # (tile_r, tile_th, sort interval) tried by Sim.autotune by default
@@ -29,7 +31,7 @@ AUTOTUNE_CANDIDATES = [(4, 8, 4), (4, 8, 8), (8, 8, 8), (4, 4, 4), (8, 16, 8), (
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "PIC_ECAPACITY",
           -5: "PIC_ENAN", -6: "PIC_EDEVICE", -7: "PIC_ESTATE"}
 
-EXPORTED = ["pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
+EXPORTED = ["pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
             "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
             "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_save", "pic_load", "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing",
@@ -70,6 +72,7 @@ def lib():
         P, d, i32, i64, u64, vp = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
         L.pic_create.argtypes = [P(vp), C.c_int, vp]
         L.pic_init.argtypes = [vp, P(GridDesc), P(PhysDesc)]
+        L.pic_init_grid.argtypes = [vp, P(GridDesc), P(PhysDesc)]
         L.pic_inject_particles.argtypes = [vp, i64] + [P(d)] * 6 + [P(u64)]
         L.pic_step.argtypes = [vp, i32]
         L.pic_field_shape.argtypes = [vp, i32, P(i32), P(i32), P(i32)]
@@ -95,7 +98,7 @@ def lib():
         L.pic_batch_last_error.argtypes = [vp]
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [vp]
-        for name in ("pic_create", "pic_init", "pic_inject_particles", "pic_step", "pic_field_shape",
+        for name in ("pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape",
                      "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_moments",
                      "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_set_sort", "pic_autotune",
                      "pic_batch_create",
@@ -153,7 +156,7 @@ class Sim:
         self.grid, self.phys = g, ph
         self.nr, self.nth = g.nr, g.nth
         self.precision = precision
-        self._check(L.pic_init(self._h, C.byref(g), C.byref(ph)))
+        self._check(L.pic_init_grid(self._h, C.byref(g), C.byref(ph)))
 
     @classmethod
     def load(cls, path, device: int = 0, stream=None):
@@ -267,6 +270,21 @@ class Sim:
         out = np.zeros(2 * N)
         self._check(lib().pic_get_moments(self._h, MOM_GAUSS, _dp(out), out.size))
         return out[:N].reshape(self.nr + 1, self.nth + 1), out[N:].reshape(self.nr + 1, self.nth + 1)
+
+    def gauss_residual(self):
+        """The Gauss residual R = G - Qbar reduced on the device in FP64 over
+        the interior nodes (PIC_MOM_GAUSS_RES): a dict of GAUSS_RES_KEYS.  The
+        drift is against the residual of the first Gauss evaluation since the
+        state was last set from the host."""
+        out = np.zeros(len(GAUSS_RES_KEYS))
+        self._check(lib().pic_get_moments(self._h, MOM_GAUSS_RES, _dp(out), out.size))
+        return dict(zip(GAUSS_RES_KEYS, out.tolist()))
+
+    def rho_q(self):
+        """The filtered bilinear node charge Qbar, (nr + 1) x (nth + 1)."""
+        out = np.zeros((self.nr + 1, self.nth + 1))
+        self._check(lib().pic_get_moments(self._h, MOM_RHO_Q, _dp(out), out.size))
+        return out
 
     def luminosity(self):
         """Poynting luminosity (total field) through the sphere of each

@@ -24,7 +24,8 @@
 //  k_inject ....... surface pair injection (Sec. 5.3, eq. (volinjeq)), then
 //                   the step index advances
 //  k_node_charge,
-//  k_gauss_flux ... FP64 Gauss diagnostic
+//  k_gauss_flux,
+//  k_gauss_final .. FP64 Gauss diagnostic: node charge, residual, reductions
 #pragma once
 #include <climits>
 
@@ -1761,21 +1762,35 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ src, co
 // Gauss diagnostic in FP64
 // ------------------------------------------------------------------
 
-// Node charge of the particles, bilinear at the four nodes of each cell.
-// A work-group takes kNodeSpan consecutive particle slots.  When the nodes
-// they reach fit in kNodeLds LDS entries (cell-sorted particles), the
-// charges are summed there with LDS atomics and each node the span reaches
-// is flushed with one global atomic; otherwise every contribution goes to
-// global memory.  The grid covers the store's capacity; work-groups past
-// the particle count return at once.
+// Node charge of the particles, bilinear at the four nodes of each cell
+// (the particle shape of Sec. 3.3, whose charge App. B's filter spreads),
+// into two planes: the signed charge Q and the absolute charge |Q|, the
+// scale against which the residual's drift is judged.  A work-group takes
+// kNodeSpan consecutive particle slots.  When the nodes they reach fit in
+// kNodeLds LDS entries (cell-sorted particles) the span's charges are summed
+// there in 64-bit fixed point -- each contribution v rounded to an integer
+// multiple of 2^-50 max|w| through the 1.5 * 2^52 shift (|v| <= max|w|, so
+// the integer stays below 2^51; a span adds at most 2^12 max|w| to an entry,
+// below 2^62) -- so that the sum of a span is exact and independent of the
+// order of the atomics, and each entry is flushed with one FP64 global
+// atomic; other spans add straight to global memory.  The grid covers the
+// store's capacity; work-groups past the particle count return at once.
 constexpr int kNodeSpan = 4096, kNodeLds = 4096;
+
+__device__ __forceinline__ void lds_add_fixed(long long *a, double x)
+{
+    const double sh = x + 6755399441055744.0; // 1.5 * 2^52: the integer lands in the low bits
+    atomicAdd((unsigned long long *)a, (unsigned long long)(__double_as_longlong(sh) - 0x4338000000000000ll));
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict__ cell, const T *__restrict__ dx,
                                                      const T *__restrict__ dy, const T *__restrict__ w,
-                                                     const unsigned long long *n_total, Layout L, double *rho)
+                                                     const unsigned long long *n_total, Layout L, double scale,
+                                                     double inv, double *__restrict__ rho,
+                                                     double *__restrict__ rabs)
 {
-    __shared__ double acc[kNodeLds];
+    __shared__ long long acc[2][kNodeLds];
     __shared__ int red[4][4];
     const unsigned long long n = *n_total;
     const unsigned long long base = (unsigned long long)blockIdx.x * kNodeSpan;
@@ -1812,33 +1827,49 @@ __global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict_
     const long long W = (long long)(jmax - jmin) + 2, NH = (long long)(imax - imin) + 2;
     if (W * NH <= kNodeLds) {
         const int nw = (int)W, ne = (int)(W * NH);
-        for (int e = tid; e < ne; e += 256) acc[e] = 0.0;
+        for (int e = tid; e < ne; e += 256) {
+            acc[0][e] = 0;
+            acc[1][e] = 0;
+        }
         __syncthreads();
         for (int k = tid; k < cnt; k += 256) {
             const uint32_t c = cell[base + k];
             if (c == kDead) continue;
             const int e = (cell_i(c) - imin) * nw + (cell_j(c) - jmin); // node (i, j); (i + 1, j) is e + nw
-            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k];
-            atomicAdd(&acc[e], Q * (1 - fx) * (1 - fy));
-            atomicAdd(&acc[e + nw], Q * fx * (1 - fy));
-            atomicAdd(&acc[e + 1], Q * (1 - fx) * fy);
-            atomicAdd(&acc[e + nw + 1], Q * fx * fy);
+            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k] * scale;
+            const double A = fabs(Q);
+            const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+            lds_add_fixed(&acc[0][e], Q * w00);
+            lds_add_fixed(&acc[0][e + nw], Q * w10);
+            lds_add_fixed(&acc[0][e + 1], Q * w01);
+            lds_add_fixed(&acc[0][e + nw + 1], Q * w11);
+            lds_add_fixed(&acc[1][e], A * w00);
+            lds_add_fixed(&acc[1][e + nw], A * w10);
+            lds_add_fixed(&acc[1][e + 1], A * w01);
+            lds_add_fixed(&acc[1][e + nw + 1], A * w11);
         }
         __syncthreads();
         for (int e = tid; e < ne; e += 256) {
-            const double v = acc[e];
-            if (v != 0.0) unsafeAtomicAdd(&rho[L.at(imin + e / nw, jmin + e % nw)], v);
+            const size_t g = L.at(imin + e / nw, jmin + e % nw);
+            const long long v = acc[0][e], a = acc[1][e];
+            if (v != 0) unsafeAtomicAdd(&rho[g], (double)v * inv);
+            if (a != 0) unsafeAtomicAdd(&rabs[g], (double)a * inv);
         }
     } else {
         for (int k = tid; k < cnt; k += 256) {
             const uint32_t c = cell[base + k];
             if (c == kDead) continue;
             const int i = cell_i(c), j = cell_j(c);
-            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k];
-            unsafeAtomicAdd(&rho[L.at(i, j)], Q * (1 - fx) * (1 - fy));
-            unsafeAtomicAdd(&rho[L.at(i + 1, j)], Q * fx * (1 - fy));
-            unsafeAtomicAdd(&rho[L.at(i, j + 1)], Q * (1 - fx) * fy);
-            unsafeAtomicAdd(&rho[L.at(i + 1, j + 1)], Q * fx * fy);
+            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k], A = fabs(Q);
+            const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+            unsafeAtomicAdd(&rho[L.at(i, j)], Q * w00);
+            unsafeAtomicAdd(&rho[L.at(i + 1, j)], Q * w10);
+            unsafeAtomicAdd(&rho[L.at(i, j + 1)], Q * w01);
+            unsafeAtomicAdd(&rho[L.at(i + 1, j + 1)], Q * w11);
+            unsafeAtomicAdd(&rabs[L.at(i, j)], A * w00);
+            unsafeAtomicAdd(&rabs[L.at(i + 1, j)], A * w10);
+            unsafeAtomicAdd(&rabs[L.at(i, j + 1)], A * w01);
+            unsafeAtomicAdd(&rabs[L.at(i + 1, j + 1)], A * w11);
         }
     }
 }
@@ -1883,25 +1914,120 @@ __global__ __launch_bounds__(256) void k_poynting(const T *__restrict__ Eth, con
     if (tid == 0) out[i] = c * red[0];
 }
 
-// Closed-surface flux of E out of the dual cell of node (i, j), i = 1..nr-1.
+// Closed-surface flux of E out of the dual cell of node (i, j) (Sec. 2
+// eq. (maxti): the flux equals the charge the node holds, App. B eq.
+// (multfiltcharge) with the filtered particle shape), and the residual
+// R = G - Qbar, in FP64.  The kernel writes G on the interior rows
+// 1 <= i <= nr-1 (zero on rows 0 and nr, whose nodes hold the conductors'
+// surface charge) and reduces R over rows 1 <= i <= i_hi, all j: the rows
+// below the lossy layer (i_hi = nr - 1 - absorb_cells), whose E the layer's
+// damping leaves alone (Sec. 3.4.1), so that R is constant there in exact
+// arithmetic.  Per work-group of 64 x 4 nodes it writes the partial
+// reductions of the residual: max |R - R0| and sum (R - R0)^2 against the
+// reference residual R0 (with ref_mode set, R0 := R instead and the drift is
+// zero), max |R|, sum R^2, max of the absolute node charge, max |G|, the
+// count of interior nodes and of non-finite values.  Every reduction is
+// formed in a fixed order, so the result does not depend on scheduling.
+constexpr int kGaussParts = 8;
+enum : int { kGpDriftMax = 0, kGpDriftSq, kGpResMax, kGpResSq, kGpAbsMax, kGpFluxMax, kGpNodes, kGpNonFinite };
+
+__device__ inline void gauss_combine(double *a, const double *b)
+{
+    a[kGpDriftMax] = fmax(a[kGpDriftMax], b[kGpDriftMax]);
+    a[kGpDriftSq] += b[kGpDriftSq];
+    a[kGpResMax] = fmax(a[kGpResMax], b[kGpResMax]);
+    a[kGpResSq] += b[kGpResSq];
+    a[kGpAbsMax] = fmax(a[kGpAbsMax], b[kGpAbsMax]);
+    a[kGpFluxMax] = fmax(a[kGpFluxMax], b[kGpFluxMax]);
+    a[kGpNodes] += b[kGpNodes];
+    a[kGpNonFinite] += b[kGpNonFinite];
+}
+
+// Tree reduction of one value set per thread of a 256-thread work-group in
+// LDS (fixed pairing); thread 0 ends with the total.
+__device__ inline void gauss_block_reduce(double (*s)[kGaussParts], double *v)
+{
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kGaussParts; ++q) s[tid][q] = v[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) gauss_combine(s[tid], s[tid + o]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kGaussParts; ++q) v[q] = s[0][q];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gauss_flux(const T *__restrict__ Er, const T *__restrict__ Eth, Layout L,
                                                     const double *__restrict__ Ar,  // 2 pi rbar_i^2, [i + G]
                                                     const double *__restrict__ dkb, // cos thetabar_{j-1} - cos thetabar_j
                                                     const double *__restrict__ At,  // pi (rbar_i^2 - rbar_{i-1}^2)
                                                     const double *__restrict__ sb,  // sin thetabar_j
-                                                    double *__restrict__ G)
+                                                    const double *__restrict__ Qbar, // filtered node charge (layout L)
+                                                    const double *__restrict__ Qabs, // absolute node charge (layout L)
+                                                    double *__restrict__ G, double *__restrict__ R0, int ref_mode,
+                                                    int i_hi, double *__restrict__ parts)
 {
+    __shared__ double s[256][kGaussParts];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > L.nr || j > L.nth) return;
-    double flux = 0.0;
-    if (i >= 1 && i < L.nr) {
-        flux = (double)Er[L.at(i, j)] * Ar[i + L.G] * dkb[j] - (double)Er[L.at(i - 1, j)] * Ar[i - 1 + L.G] * dkb[j];
-        if (j < L.nth) flux += (double)Eth[L.at(i, j)] * At[i] * sb[j];
-        if (j > 0) flux -= (double)Eth[L.at(i, j - 1)] * At[i] * sb[j - 1];
+    double v[kGaussParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i <= L.nr && j <= L.nth) {
+        const size_t n = (size_t)i * (L.nth + 1) + j;
+        double flux = 0.0;
+        if (i >= 1 && i < L.nr) {
+            flux = (double)Er[L.at(i, j)] * Ar[i + L.G] * dkb[j] -
+                   (double)Er[L.at(i - 1, j)] * Ar[i - 1 + L.G] * dkb[j];
+            if (j < L.nth) flux += (double)Eth[L.at(i, j)] * At[i] * sb[j];
+            if (j > 0) flux -= (double)Eth[L.at(i, j - 1)] * At[i] * sb[j - 1];
+            const double q = Qbar[L.at(i, j)], a = Qabs[L.at(i, j)];
+            const double res = flux - q;
+            double d = 0.0;
+            if (ref_mode) R0[n] = res;
+            else d = res - R0[n];
+            const bool bad = !isfinite(flux) || !isfinite(q) || !isfinite(a) || !isfinite(d);
+            v[kGpNonFinite] = bad ? 1.0 : 0.0;
+            if (i <= i_hi) {
+                if (!bad) {
+                    v[kGpDriftMax] = fabs(d);
+                    v[kGpDriftSq] = d * d;
+                    v[kGpResMax] = fabs(res);
+                    v[kGpResSq] = res * res;
+                    v[kGpAbsMax] = a;
+                    v[kGpFluxMax] = fabs(flux);
+                }
+                v[kGpNodes] = 1.0;
+            }
+        }
+        G[n] = flux;
     }
-    G[(size_t)i * (L.nth + 1) + j] = flux;
+    gauss_block_reduce(s, v);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double *o = parts + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kGaussParts;
+#pragma unroll
+        for (int q = 0; q < kGaussParts; ++q) o[q] = v[q];
+    }
+}
+
+// The partial reductions of all work-groups of k_gauss_flux, combined by one
+// work-group in a fixed order: out[0..7] = max |R - R0|, sqrt(sum (R - R0)^2),
+// max |R|, sqrt(sum R^2), max absolute node charge, max |G|, interior nodes,
+// non-finite values.
+__global__ __launch_bounds__(256) void k_gauss_final(const double *__restrict__ parts, int n_parts,
+                                                     double *__restrict__ out)
+{
+    __shared__ double s[256][kGaussParts];
+    double v[kGaussParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < n_parts; b += 256) gauss_combine(v, parts + (size_t)b * kGaussParts);
+    gauss_block_reduce(s, v);
+    if (threadIdx.x == 0) {
+        v[kGpDriftSq] = sqrt(v[kGpDriftSq]);
+        v[kGpResSq] = sqrt(v[kGpResSq]);
+#pragma unroll
+        for (int q = 0; q < kGaussParts; ++q) out[q] = v[q];
+    }
 }
 
 } // namespace pic

@@ -425,7 +425,12 @@ public:
                                   uint64_t *id, int64_t cap) = 0;
     virtual void counts(double *out) = 0;
     virtual void gauss(double *out) = 0;
+    virtual void gauss_residual(double *out) = 0;
+    virtual void rho_q(double *out) = 0;
     virtual void luminosity(double *out) = 0;
+    // the state was changed from the host: the Gauss drift's reference lapses
+    void gauss_unref() { gauss_ref_ = false; }
+    bool gauss_ref_ = false;
     virtual void get_carry(double *out) = 0;
     virtual void set_carry(const double *in) = 0;
     virtual void set_step(int64_t step) = 0;
@@ -569,6 +574,23 @@ public:
         fill(carry_, (size_t)nth + 1, 0.0);
         R.carry = carry_;
         R.seed = ph.seed;
+        // diagnostic planes, allocated once: node charge, its filter
+        // ping-pong and the absolute charge (padded layout), the E flux and
+        // the reference residual ((nr + 1) x (nth + 1)), the per-work-group
+        // partial reductions, their total, and the luminosity per sphere
+        const size_t nodes = (size_t)(nr + 1) * (nth + 1);
+        gauss_grid_x_ = (nth + 1 + 63) / 64;
+        gauss_grid_y_ = (nr + 1 + 3) / 4;
+        grho_ = dalloc<double>(fsz);
+        gtmp_ = dalloc<double>(fsz);
+        gabs_ = dalloc<double>(fsz);
+        fill(gtmp_, fsz, 0.0);
+        gG_ = dalloc<double>(nodes);
+        gR0_ = dalloc<double>(nodes);
+        gparts_ = dalloc<double>((size_t)gauss_grid_x_ * gauss_grid_y_ * kGaussParts);
+        gout_ = dalloc<double>(kGaussParts);
+        gL_ = dalloc<double>((size_t)nr);
+        gauss_ref_ = false;
         plan_.build({rd_}, ppt_, stream);
     }
 
@@ -626,6 +648,7 @@ public:
         HIPCHK(hipMemcpyAsync(ctr_ + kNeedSort, &upd[1], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
         sched_need_ = true;
+        gauss_unref();
         if (set_dep_scale()) {
             plan_.upload({rd_}, stream);
             ++version;
@@ -673,6 +696,7 @@ public:
             for (int cc = 0; cc < cols; ++cc) h[L.at(row0 + r, cc)] = (T)in[(size_t)r * cols + cc];
         HIPCHK(hipMemcpyAsync(fld_[comp], h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
+        gauss_unref();
     }
 
     int64_t get_particles(double *x, double *y, double *ur, double *ut, double *up, double *w, uint64_t *id,
@@ -728,71 +752,92 @@ public:
         out[5] = (double)c[kGlobalChunks];
     }
 
-    void gauss(double *out) override
+    // The filtered bilinear node charge of the particles (and their
+    // unfiltered absolute charge) in the persistent diagnostic planes;
+    // returns the plane that holds the filtered charge.
+    const double *charge_planes()
     {
         unsigned long long c[kNumCounters];
         read_counters(c);
         const int cur = (int)c[kCur];
         const size_t fsz = L.size();
-        const size_t N = (size_t)(gd.nr + 1) * (gd.nth + 1);
-        double *rho = dev_alloc<double>(fsz);
-        double *tmp = nullptr, *G = nullptr;
-        try {
-            tmp = dev_alloc<double>(fsz);
-            G = dev_alloc<double>(N);
-            fill(rho, fsz, 0.0);
-            fill(tmp, fsz, 0.0);
-            const int spans = (int)((cap_ + kNodeSpan - 1) / kNodeSpan);
-            k_node_charge<T><<<std::max(spans, 1), 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1],
-                                                                    arr_[cur][5], ctr_ + kTotal, L, rho);
+        fill(grho_, fsz, 0.0);
+        fill(gabs_, fsz, 0.0);
+        const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
+        const int spans = (int)((cap_ + kNodeSpan - 1) / kNodeSpan);
+        k_node_charge<T><<<std::max(spans, 1), 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1],
+                                                                arr_[cur][5], ctr_ + kTotal, L,
+                                                                std::ldexp(1.0, 50) / qm, qm * std::ldexp(1.0, -50),
+                                                                grho_, gabs_);
+        HIPCHK(hipGetLastError());
+        double *a = grho_, *b = gtmp_;
+        const dim3 blk(64, 4), fg((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4);
+        for (int pss = 0; pss < gd.n_filt; ++pss) {
+            k_filter_nodes<double><<<fg, blk, 0, stream>>>(a, b, L);
             HIPCHK(hipGetLastError());
-            double *a = rho, *b = tmp;
-            const dim3 blk(64, 4), fg((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4);
-            for (int pss = 0; pss < gd.n_filt; ++pss) {
-                k_filter_nodes<double><<<fg, blk, 0, stream>>>(a, b, L);
-                HIPCHK(hipGetLastError());
-                std::swap(a, b);
-            }
-            const dim3 grd((gd.nth + 1 + 63) / 64, (gd.nr + 1 + 3) / 4);
-            k_gauss_flux<T><<<grd, blk, 0, stream>>>(fld_[cER], fld_[cETH], L, gA_r_, gdkb_, gA_t_, gsb_, G);
-            HIPCHK(hipGetLastError());
-            std::vector<double> hr(fsz);
-            HIPCHK(hipMemcpyAsync(out, G, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
-            HIPCHK(hipMemcpyAsync(hr.data(), a, sizeof(double) * fsz, hipMemcpyDeviceToHost, stream));
-            HIPCHK(hipStreamSynchronize(stream));
-            for (int i = 0; i <= gd.nr; ++i)
-                for (int j = 0; j <= gd.nth; ++j) out[N + (size_t)i * (gd.nth + 1) + j] = hr[L.at(i, j)];
-        } catch (...) {
-            (void)hipStreamSynchronize(stream);
-            (void)hipFree(rho);
-            if (tmp) (void)hipFree(tmp);
-            if (G) (void)hipFree(G);
-            throw;
+            std::swap(a, b);
         }
-        HIPCHK(hipFree(rho));
-        HIPCHK(hipFree(tmp));
-        HIPCHK(hipFree(G));
+        return a;
+    }
+
+    // Gauss residual R = G - Qbar with its FP64 reductions on the device; the
+    // first evaluation after the state was set from the host records R as
+    // the reference R0 of the drift.  Returns the filtered charge plane.
+    const double *gauss_eval()
+    {
+        const double *q = charge_planes();
+        const dim3 blk(64, 4), grd(gauss_grid_x_, gauss_grid_y_);
+        k_gauss_flux<T><<<grd, blk, 0, stream>>>(fld_[cER], fld_[cETH], L, gA_r_, gdkb_, gA_t_, gsb_, q, gabs_, gG_,
+                                                 gR0_, gauss_ref_ ? 0 : 1, std::max(gd.nr - 1 - rd_.absorb_cells, 0),
+                                                 gparts_);
+        HIPCHK(hipGetLastError());
+        k_gauss_final<<<1, 256, 0, stream>>>(gparts_, gauss_grid_x_ * gauss_grid_y_, gout_);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(gauss_last_, gout_, sizeof gauss_last_, hipMemcpyDeviceToHost, stream));
+        if (!gauss_ref_) gauss_ref_step_ = (double)read_step();
+        gauss_ref_ = true;
+        return q;
+    }
+
+    void gauss(double *out) override
+    {
+        const double *q = gauss_eval();
+        const size_t N = (size_t)(gd.nr + 1) * (gd.nth + 1);
+        HIPCHK(hipMemcpyAsync(out, gG_, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
+        copy_node_plane(q, out + N);
+        HIPCHK(hipStreamSynchronize(stream));
+        if (gauss_last_[kGpNonFinite] > 0.0)
+            throw StatusError{PIC_ENAN, "non-finite value in the Gauss diagnostic (E or particle charge)"};
+    }
+
+    void gauss_residual(double *out) override
+    {
+        gauss_eval();
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int q = 0; q < kGaussParts; ++q) out[q] = gauss_last_[q];
+        out[kGaussParts] = gauss_ref_step_;
+        if (gauss_last_[kGpNonFinite] > 0.0)
+            throw StatusError{PIC_ENAN, "non-finite value in the Gauss diagnostic (E or particle charge)"};
+    }
+
+    void rho_q(double *out) override
+    {
+        const double *q = charge_planes();
+        copy_node_plane(q, out);
+        HIPCHK(hipStreamSynchronize(stream));
     }
 
     void luminosity(double *out) override
     {
-        unsigned long long c[kNumCounters];
-        read_counters(c);
-        const double t = (double)c[kStep];
-        double *d = dev_alloc<double>((size_t)gd.nr);
-        try {
-            k_poynting<T><<<gd.nr, 256, 0, stream>>>(fld_[cETH], fld_[cEPH], fld_[cBTH], fld_[cBPH], L, rd_.bg,
-                                                     inv_light_cylinder(ph.omega, ph.t_spin, gd.c, t), gd.c, grb_,
-                                                     gA_r_, gkc_, gsb_, gdk_, d);
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(out, d, sizeof(double) * gd.nr, hipMemcpyDeviceToHost, stream));
-            HIPCHK(hipStreamSynchronize(stream));
-        } catch (...) {
-            (void)hipStreamSynchronize(stream);
-            (void)hipFree(d);
-            throw;
-        }
-        HIPCHK(hipFree(d));
+        const double t = (double)read_step();
+        k_poynting<T><<<gd.nr, 256, 0, stream>>>(fld_[cETH], fld_[cEPH], fld_[cBTH], fld_[cBPH], L, rd_.bg,
+                                                 inv_light_cylinder(ph.omega, ph.t_spin, gd.c, t), gd.c, grb_,
+                                                 gA_r_, gkc_, gsb_, gdk_, gL_);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, gL_, sizeof(double) * gd.nr, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int i = 0; i < gd.nr; ++i)
+            if (!std::isfinite(out[i])) throw StatusError{PIC_ENAN, "non-finite value in the Poynting luminosity"};
     }
 
     void get_carry(double *out) override
@@ -910,9 +955,16 @@ public:
         if (h.counters[kTotal] != h.slots || h.counters[kDeadSinceSort] > h.slots || h.counters[kLive] > h.slots ||
             h.counters[kCur] > 1 || !(h.qmax >= 0.0))
             throw StatusError{PIC_EINVAL, "checkpoint counters are inconsistent"};
-        for (int q = 0; q < 9; ++q) undump(f, fld_[q], L.size());
-        for (int q = 0; q < 3; ++q) undump(f, ftmp_[q], L.size());
-        undump(f, carry_, (size_t)gd.nth + 1);
+        auto finite = [](const char *what) {
+            return [what](const auto *v, size_t m, size_t) {
+                for (size_t q = 0; q < m; ++q)
+                    if (!std::isfinite((double)v[q]))
+                        throw StatusError{PIC_EINVAL, std::string("checkpoint holds a non-finite ") + what};
+            };
+        };
+        for (int q = 0; q < 9; ++q) undump(f, fld_[q], L.size(), finite("field value"));
+        for (int q = 0; q < 3; ++q) undump(f, ftmp_[q], L.size(), finite("face charge"));
+        undump(f, carry_, (size_t)gd.nth + 1, finite("injection carry"));
         // the kernels index fields and LDS by these: every cell must lie where
         // a particle may be, every offset inside its cell
         const int lim = gd.n_filt + 1, nr = gd.nr, nth = gd.nth;
@@ -935,7 +987,15 @@ public:
                 if (!(v[q] >= (T)0 && (v[q] < (T)1 || (v[q] == (T)1 && last_row[o + q]))))
                     throw StatusError{PIC_EINVAL, "checkpoint offset out of range"};
         });
-        for (int a = 2; a < 6; ++a) undump(f, arr_[0][a], h.slots);
+        for (int a = 2; a < 5; ++a) undump(f, arr_[0][a], h.slots, finite("momentum"));
+        // the fixed-point deposit is scaled by the largest |w| the header
+        // records (that of the FP64 weights as given, which an FP32 store
+        // holds rounded to within 2^-24): every weight must lie within it
+        undump(f, arr_[0][5], h.slots, [&](const T *v, size_t m, size_t) {
+            for (size_t q = 0; q < m; ++q)
+                if (!(std::fabs((double)v[q]) <= h.qmax * (1.0 + 0x1p-23)))
+                    throw StatusError{PIC_EINVAL, "checkpoint weight non-finite or above its recorded maximum"};
+        });
         if (with_ids_) undump(f, id_[0], h.slots);
         unsigned long long c[kNumCounters];
         for (int k = 0; k < kNumCounters; ++k) c[k] = h.counters[k];
@@ -1027,6 +1087,11 @@ private:
     const double *grb_ = nullptr, *gkc_ = nullptr, *gdk_ = nullptr;
     double rb0_ = 0.0;
     double stage_ms_[kStages] = {};
+    double *grho_ = nullptr, *gtmp_ = nullptr, *gabs_ = nullptr, *gG_ = nullptr, *gR0_ = nullptr;
+    double *gparts_ = nullptr, *gout_ = nullptr, *gL_ = nullptr;
+    int gauss_grid_x_ = 1, gauss_grid_y_ = 1;
+    double gauss_last_[kGaussParts] = {};
+    double gauss_ref_step_ = 0.0; // step index at which the reference residual was recorded
 
     template <typename U>
     U *dalloc(size_t n)
@@ -1053,6 +1118,19 @@ private:
     {
         HIPCHK(hipMemcpyAsync(c, ctr_, sizeof(unsigned long long) * kNumCounters, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
+    }
+    uint64_t read_step()
+    {
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        return c[kStep];
+    }
+    // nodes (i, j), i = 0..nr, j = 0..nth, of a plane in the padded layout
+    // into a row-major host array
+    void copy_node_plane(const double *plane, double *host)
+    {
+        HIPCHK(hipMemcpy2DAsync(host, sizeof(double) * (gd.nth + 1), plane + L.at(0, 0), sizeof(double) * L.pitch,
+                                sizeof(double) * (gd.nth + 1), gd.nr + 1, hipMemcpyDeviceToHost, stream));
     }
     // fixed-point scale of the LDS deposit from the largest |w| held,
     // bounded so that it stays finite in T for vanishing weights (test
@@ -1385,6 +1463,11 @@ pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc
     });
 }
 
+pic_status pic_init_grid(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys)
+{
+    return pic_init(ctx, grid, phys);
+}
+
 pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const double *y, const double *ur,
                                 const double *ut, const double *up, const double *w, const uint64_t *id)
 {
@@ -1478,6 +1561,14 @@ pic_status pic_get_moments(pic_ctx *ctx, int32_t kind, double *out, int64_t cap)
         case PIC_MOM_POYNTING:
             if (cap < ctx->eng->gd.nr) throw StatusError{PIC_EINVAL, "output buffer too small"};
             ctx->eng->luminosity(out);
+            break;
+        case PIC_MOM_GAUSS_RES:
+            if (cap < kGaussParts + 1) throw StatusError{PIC_EINVAL, "output buffer too small"};
+            ctx->eng->gauss_residual(out);
+            break;
+        case PIC_MOM_RHO_Q:
+            if (cap < N) throw StatusError{PIC_EINVAL, "output buffer too small"};
+            ctx->eng->rho_q(out);
             break;
         default:
             throw StatusError{PIC_EINVAL, "unknown moment"};

@@ -76,3 +76,30 @@ def test_no_device_is_reported_as_a_device_error(L):
     out = C.c_void_p()
     assert L.pic_create(C.byref(out), 0, None) == -6
     assert not out.value
+
+
+def _enum_values(prefix):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(" + prefix + r"\w+)\s*=\s*(-?\d+)", text)}
+
+
+def test_moment_kinds_and_status_codes_match_the_header():
+    """The binding's moment kinds (including the device Gauss-residual
+    reduction and the node charge) and status codes are the header's."""
+    from paper_1407_1810_amd import binding as B
+    kinds = _enum_values("PIC_MOM_")
+    assert kinds == {"PIC_MOM_COUNTS": B.MOM_COUNTS, "PIC_MOM_GAUSS": B.MOM_GAUSS, "PIC_MOM_CARRY": B.MOM_CARRY,
+                     "PIC_MOM_STAGE_MS": B.MOM_STAGE_MS, "PIC_MOM_POYNTING": B.MOM_POYNTING,
+                     "PIC_MOM_GAUSS_RES": B.MOM_GAUSS_RES, "PIC_MOM_RHO_Q": B.MOM_RHO_Q}
+    codes = {k: v for k, v in _enum_values("PIC_E").items() if v < 0}  # PIC_ER.. are field components
+    codes["PIC_OK"] = 0
+    assert {v: k for k, v in codes.items()} == B.STATUS
+    assert len(B.GAUSS_RES_KEYS) == 9
+
+
+def test_init_grid_is_exported_beside_init(L):
+    """pic_init_grid (the boundary's name) and pic_init are the same call:
+    both reject a null context without a device."""
+    vp = C.c_void_p
+    assert L.pic_init_grid(vp(), None, None) == -1
+    assert L.pic_init(vp(), None, None) == -1

@@ -4,14 +4,18 @@ surface injection, relaxes to Michel's force-free wind, in which the field
 lines wind up as B_phi / B_r = -r sin(theta) / R_l and the field is
 E_theta = B_phi inside the light cylinder R_l = c / Omega.
 
-The check runs a 48 x 48 log-r, equal-area grid (r_out = 12 r_in,
-R_l = 3 r_in, spin-up time 1/Omega) for two rotation periods.  The paper
-shows the agreement only in figures, so the bounds are ours: at 0.35, 0.5
-and 0.7 R_l the median over the latitudes away from the poles of the
-winding's ratio to Michel's, and of E_theta / B_phi, within 15 % of one,
-and the Poynting luminosity through spheres at 0.35 and 0.5 R_l within 15 % of
-Michel's L_0 = (8 pi / 3) c (B0 r_in^2 / R_l)^2 (Lorentz-Heaviside units;
-the paper quotes about 1 % for its far finer runs).
+The check runs a log-r, equal-area grid (r_out = 12 r_in, R_l = 3 r_in,
+spin-up time 1/Omega) for two rotation periods, at 48 x 48 and at 96 x 96
+cells.  The paper shows the agreement only in figures (and quotes about 1 %
+for the luminosity of its far finer runs), so the bounds are ours, set from
+what each resolution reaches: at 0.35, 0.5 and 0.7 R_l the median over the
+latitudes away from the poles of the winding's ratio to Michel's and of
+E_theta / B_phi, and the Poynting luminosity through spheres at 0.35 and 0.5
+R_l against Michel's L_0 = (8 pi / 3) c (B0 r_in^2 / R_l)^2
+(Lorentz-Heaviside units).  At 48 x 48 (measured: winding 7-10 % low,
+E_theta / B_phi 5-9 % high, L 11-13 % low) within 11 %, 11 % and 14 %; at
+96 x 96 (measured: within 0.6 %, 1 % and 1.6 %) within 2.5 %, 2.5 % and 3 %:
+the wind converges to Michel's as the grid is refined.
 Every term of the step takes part (spin-up fields, injection, push,
 deposit, filter, field update, lossy layer); switching the injection off
 leaves no wound-up field at all, which the control case checks."""
@@ -74,22 +78,26 @@ def _winding(o, p, Rl, frac):
         return ratio, michel, eth / bph
 
 
-@pytest.fixture(scope="module")
-def michel_run():
-    return _run()
+# grid cells -> bounds on the winding, on E_theta / B_phi and on L / L_0
+BOUNDS = {48: (0.11, 0.11, 0.14), 96: (0.025, 0.025, 0.03)}
+
+
+@pytest.fixture(scope="module", params=[48, 96])
+def michel_run(request):
+    return _run(n=request.param) + (BOUNDS[request.param],)
 
 
 @pytest.mark.parametrize("frac", [0.35, 0.5, 0.7])
 def test_field_winds_up_as_michel(michel_run, frac):
-    o, p, Rl = michel_run
+    o, p, Rl, bounds = michel_run
     wind, e_over_b = _medians(o, p, Rl, frac)
     ratio, michel, _ = _winding(o, p, Rl, frac)
     eq = p["nth"] // 2
-    print(f"r = {frac} R_l: winding / Michel median {wind:.4f} (equator {ratio[eq] / michel[eq]:.4f}), "
-          f"E_theta / B_phi median {e_over_b:.4f}")
+    print(f"{p['nr']} cells, r = {frac} R_l: winding / Michel median {wind:.4f} "
+          f"(equator {ratio[eq] / michel[eq]:.4f}), E_theta / B_phi median {e_over_b:.4f}")
     assert ratio[eq] < 0.0
-    assert abs(wind - 1.0) < 0.15
-    assert abs(e_over_b - 1.0) < 0.15
+    assert abs(wind - 1.0) < bounds[0]
+    assert abs(e_over_b - 1.0) < bounds[1]
 
 
 def _luminosity(o, p, Rl, frac):
@@ -111,12 +119,12 @@ def _luminosity(o, p, Rl, frac):
 
 
 def test_luminosity_is_michels(michel_run):
-    o, p, Rl = michel_run
+    o, p, Rl, bounds = michel_run
     L0 = 8.0 * math.pi / 3.0 * p["c"] * (p["B0"] * p["r_in"] ** 2 / Rl) ** 2
     for frac in (0.35, 0.5):
         L = _luminosity(o, p, Rl, frac)
-        print(f"r = {frac} R_l: L / L0 = {L / L0:.4f}")
-        assert abs(L / L0 - 1.0) < 0.15
+        print(f"{p['nr']} cells, r = {frac} R_l: L / L0 = {L / L0:.4f}")
+        assert abs(L / L0 - 1.0) < bounds[2]
 
 
 def test_no_winding_without_plasma():
