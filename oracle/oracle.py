@@ -68,6 +68,7 @@ def lib():
         L.ora_set_field.argtypes = [C.c_void_p, C.c_int, P(d)]
         L.ora_get_field.argtypes = [C.c_void_p, C.c_int, P(d)]
         L.ora_add_particles.argtypes = [C.c_void_p, i64] + [P(d)] * 6 + [P(u64)]
+        L.ora_add_particles_cells.argtypes = [C.c_void_p, i64, P(i32), P(d), P(i32)] + [P(d)] * 5 + [P(u64)]
         L.ora_num_particles.restype = i64
         L.ora_num_particles.argtypes = [C.c_void_p]
         L.ora_get_particles.argtypes = [C.c_void_p] + [P(d)] * 6 + [P(u64)]
@@ -197,6 +198,18 @@ class Oracle:
             ida = np.ascontiguousarray(ids, dtype=np.uint64)
             idp = _up(ida)
         self._check(lib().ora_add_particles(self._h, n, *[_dp(a) for a in arrs], idp))
+
+    def add_particles_cells(self, ci, fx, cj, fy, ur, ut, up, w, ids=None):
+        """Particles given as cell indices and in-cell offsets."""
+        i32 = [np.ascontiguousarray(a, dtype=np.int32) for a in (ci, cj)]
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (fx, fy, ur, ut, up, w)]
+        idp = None
+        if ids is not None:
+            ida = np.ascontiguousarray(ids, dtype=np.uint64)
+            idp = _up(ida)
+        ip = [a.ctypes.data_as(C.POINTER(C.c_int32)) for a in i32]
+        self._check(lib().ora_add_particles_cells(self._h, len(arrs[0]), ip[0], _dp(arrs[0]), ip[1], _dp(arrs[1]),
+                                                  *[_dp(a) for a in arrs[2:]], idp))
 
     @property
     def n(self):

@@ -278,6 +278,32 @@ int ora_add_particles(ora_sim *s, int64_t n, const double *x, const double *y, c
     return ORA_OK;
 }
 
+/* The same from cell indices and in-cell offsets (a state stored as cell +
+ * offset): the distance to the nearer pole is formed from the offset,
+ * min(j + fy, (nth - j) - fy), before the absolute coordinate rounds it. */
+int ora_add_particles_cells(ora_sim *s, int64_t n, const int32_t *ci, const double *fx, const int32_t *cj,
+                            const double *fy, const double *ur, const double *ut, const double *up,
+                            const double *w, const uint64_t *id)
+{
+    if (!s || n < 0) return ORA_EINVAL;
+    if (reserve(s, s->n + n) != ORA_OK) return ORA_ENOMEM;
+    const int nth = s->p.nth;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t d = s->n + k;
+        s->x[d] = ci[k] + fx[k];
+        s->y[d] = cj[k] + fy[k];
+        const double north = cj[k] + fy[k], south = (double)(nth - cj[k]) - fy[k];
+        s->dp[d] = north <= south ? north : south;
+        s->ur[d] = ur[k];
+        s->ut[d] = ut[k];
+        s->up[d] = up[k];
+        s->w[d] = w[k];
+        s->id[d] = id ? id[k] : (uint64_t)d;
+    }
+    s->n += n;
+    return ORA_OK;
+}
+
 int64_t ora_num_particles(const ora_sim *s) { return s ? s->n : -1; }
 
 int ora_get_particles(const ora_sim *s, double *x, double *y, double *ur, double *ut, double *up,

@@ -77,6 +77,10 @@ int ora_get_field(const ora_sim *s, int comp, double *out);
 int ora_add_particles(ora_sim *s, int64_t n, const double *x, const double *y,
                       const double *ur, const double *ut, const double *up,
                       const double *w, const uint64_t *id);
+/* the same from cell indices (ci radial, cj meridional) and in-cell offsets */
+int ora_add_particles_cells(ora_sim *s, int64_t n, const int32_t *ci, const double *fx, const int32_t *cj,
+                            const double *fy, const double *ur, const double *ut, const double *up,
+                            const double *w, const uint64_t *id);
 int64_t ora_num_particles(const ora_sim *s);
 int ora_get_particles(const ora_sim *s, double *x, double *y, double *ur, double *ut,
                       double *up, double *w, uint64_t *id);

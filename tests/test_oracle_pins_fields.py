@@ -265,3 +265,48 @@ def test_charge_fall_in_relaxes_pointwise():
         upto = np.abs(ratio[1:nr - L - 1] - 1.0).max()
         print(f"{t_tc} crossing times: inner half {inner:.4f}, up to the layer {upto:.4f}")
         assert inner < inner_bound and upto < all_bound
+
+
+def test_cell_offset_loader_matches_absolute_coordinates():
+    """Particles handed to the oracle as cell indices plus offsets take the
+    same step as the same particles given by absolute coordinates, when the
+    absolute coordinates are exact (offsets on a 2^-20 grid); near a pole the
+    loader forms the pole distance from the offset, so a particle 2^-44 of a
+    cell from the south pole of a 2^14-cell grid keeps that distance (the
+    absolute coordinate nth - 2^-44 rounds to the pole)."""
+    p = W.grid_params(16, 12, 4.0)
+    p.update(dict(n_filt=1, absorb_cells=0, sigma_max=0.0, mover="vay", bg_kind="dipole", B0=1.0, omega=0.01,
+                  q_over_m=1.0))
+    rng = np.random.default_rng(21)
+    n = 64
+    ci = rng.integers(0, 16, n).astype(np.int32)
+    cj = rng.integers(0, 12, n).astype(np.int32)
+    fx = np.floor(rng.uniform(0, 1, n) * 2 ** 20) / 2 ** 20
+    fy = np.floor(rng.uniform(0, 1, n) * 2 ** 20) / 2 ** 20
+    u = rng.normal(0, 0.3, (3, n))
+    w = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * 1e-3
+    a, b = O.Oracle(p), O.Oracle(p)
+    a.add_particles(ci + fx, cj + fy, u[0], u[1], u[2], w)
+    b.add_particles_cells(ci, fx, cj, fy, u[0], u[1], u[2], w)
+    a.step(1)
+    b.step(1)
+    Pa, Pb = a.particles(), b.particles()
+    for k in Pa:
+        assert np.array_equal(Pa[k], Pb[k]), k
+    for c in ("Fr", "Fth", "Fph"):
+        assert np.array_equal(a.get_field(c), b.get_field(c)), c
+    # the pole distance from the offset: on a grid of 2^14 meridional cells
+    # the absolute coordinate nth - 2^-44 rounds to the pole itself, the
+    # cell-offset loader keeps the particle 2^-44 of a cell from the axis
+    q = W.grid_params(8, 2 ** 14, 4.0)
+    q.update(dict(n_filt=0, absorb_cells=0, sigma_max=0.0, mover="vay", bg_kind="dipole", B0=1.0, omega=0.01,
+                  q_over_m=1.0))
+    eps = 2.0 ** -44
+    near, absolute, pole = O.Oracle(q), O.Oracle(q), O.Oracle(q)
+    near.add_particles_cells([4], [0.5], [2 ** 14 - 1], [1.0 - eps], [0.0], [0.3], [0.0], [1e-3])
+    absolute.add_particles([4.5], [2.0 ** 14 - eps], [0.0], [0.3], [0.0], [1e-3])
+    pole.add_particles_cells([4], [0.5], [2 ** 14 - 1], [1.0], [0.0], [0.3], [0.0], [1e-3])
+    for o in (near, absolute, pole):
+        o.step(1)
+    assert np.array_equal(absolute.particles()["ur"], pole.particles()["ur"])
+    assert not np.array_equal(near.particles()["ur"], pole.particles()["ur"])
