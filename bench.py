@@ -37,7 +37,11 @@ def log(*a):
 
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1407_1810_amd", "csrc", f) for f in ("pic_device.h", "pic_kernels.h")]
-PROFILE = os.path.join(ROOT, "profiles", "k_push_dipole_rotator_1024x1024_ppc64.md")
+# committed rocprofv3 summaries (counter passes) of the push in each form
+PROFILE = "k_push_dipole_rotator_1024x1024_ppc64.md"
+PROFILE_FP64 = "k_push_fp64_dipole_rotator_1024x1024_ppc64.md"
+PROFILE_BATCH = "k_push_batched_ensemble_64_runs.md"
+PROFILE_STRESS = "k_push_precision_stress_2048x2048_ppc48.md"
 
 
 def kernel_source_hash() -> str:
@@ -47,22 +51,6 @@ def kernel_source_hash() -> str:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
-
-
-def profiled_counters() -> dict:
-    """Figures of the committed rocprofv3 summary of the push kernel
-    ('key: value' lines), or {} when the kernel sources changed since the
-    counters were taken (then they no longer describe this kernel)."""
-    if not os.path.exists(PROFILE):
-        return {}
-    vals = {}
-    for line in open(PROFILE):
-        if ":" in line and line.startswith("- `"):
-            k, v = line[3:].split("`", 1)[0], line.split(":", 1)[1].strip().rstrip(".")
-            vals[k] = v
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return {}
-    return vals
 
 
 def measured_copy_peak(mib=1024, reps=5) -> float:
@@ -87,42 +75,96 @@ def measured_copy_peak(mib=1024, reps=5) -> float:
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt):
+def auto_sort_interval(steps: int, preferred: int = 16) -> int:
+    """The sort interval the timed window is built on: the largest divisor of
+    `steps` from 8 to `preferred` (so that the window holds whole sort
+    intervals and the sort weighs in at its steady share), else `preferred`."""
+    for k in range(preferred, 7, -1):
+        if steps % k == 0:
+            return k
+    return preferred
+
+
+def sync_device():
+    """torch's view of the device, synchronised (the library synchronises
+    its own stream at the end of every pic_step)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+def roofline(bytes_launch, kernel_ms, kernel, copy_gbs, traffic=None, utilisation=None):
+    achieved = bytes_launch / (kernel_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_launch}
+    if copy_gbs:
+        out["measured_copy_peak"] = copy_gbs
+        out["frac_of_copy"] = achieved / copy_gbs
+    if utilisation is not None:
+        out["utilisation"] = utilisation
+    return out
+
+
+def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt, gauss=True, tag=None):
+    """One context on the workload: `warmup` steps, then the timed window of
+    `steps` steps replayed from the step graphs (the production path of
+    pic_step), bracketed by device synchronisations -- the value -- and then
+    a second window of the same length enqueued eagerly between HIP events on
+    the context stream, which gives each stage's mean device time and the
+    push kernel's duration for the roofline.  Both windows span whole sort
+    intervals."""
     from paper_1407_1810_amd.binding import Sim
+    tag = tag or precision
     p = cfg["params"]
     n = len(P["x"])
     cap = n + 16 * (1 << 20)
     s = Sim(p, precision=precision, capacity=cap, ids=False, tile=tile, sort_interval=sort_interval, chunk_ppt=ppt)
     t0 = time.perf_counter()
     s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"])
-    log(f"[{precision}] loaded {n} particles in {time.perf_counter() - t0:.1f} s")
+    log(f"[{tag}] loaded {n} particles in {time.perf_counter() - t0:.1f} s")
     s.step(warmup)
-    log(f"[{precision}] warmup {warmup} steps done")
-    s.set_timing(True)
+    log(f"[{tag}] warmup {warmup} steps done")
     c0 = s.counts()
+    sync_device()
     t0 = time.perf_counter()
     s.step(steps)
-    t1 = time.perf_counter()
+    sync_device()
+    wall = time.perf_counter() - t0
     c1 = s.counts()
+    # the same number of steps again, eagerly between HIP events
+    s.set_timing(True)
+    t1 = time.perf_counter()
+    s.step(steps)
+    wall_e = time.perf_counter() - t1
+    c2 = s.counts()
     st = s.stage_ms()
     s.set_timing(False)
     psteps = c1["particle_steps"] - c0["particle_steps"]
-    wall = t1 - t0
     res = dict(value=psteps / wall, ms_per_step=1e3 * wall / steps, particle_steps=psteps,
                mean_live=psteps / steps, stage_ms=st, live_end=c1["live"], injected=c1["injected"],
-               deleted=c1["deleted"])
-    log(f"[{precision}] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
-        f"stages {json.dumps({k: round(v, 4) for k, v in st.items()})}")
-    # the Gauss-law residual (an occasional diagnostic, outside the timed
-    # steps): one whole PIC_MOM_GAUSS_RES call -- node charge, filter passes,
-    # FP64 flux and residual reductions on the device, the scalars copied to
-    # the host -- the second of two calls (the first records the reference)
-    for _ in range(2):
-        t0 = time.perf_counter()
-        g = s.gauss_residual()
-        res["gauss_diagnostic_ms"] = 1e3 * (time.perf_counter() - t0)
-    res["gauss"] = {k: g[k] for k in ("drift_max", "res_max", "abs_charge_max", "flux_max", "nodes", "non_finite")}
-    log(f"[{precision}] Gauss residual diagnostic: {res['gauss_diagnostic_ms']:.2f} ms per call, {res['gauss']}")
+               deleted=c1["deleted"], sort_interval=sort_interval,
+               eager_ms_per_step=1e3 * wall_e / steps,
+               eager_mean_live=(c2["particle_steps"] - c1["particle_steps"]) / steps,
+               global_chunks=c2["global_chunks"])
+    log(f"[{tag}] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step "
+        f"(graph); eager {res['eager_ms_per_step']:.3f} ms/step, stages "
+        f"{json.dumps({k: round(v, 4) for k, v in st.items()})}")
+    if gauss:
+        # the Gauss-law residual (an occasional diagnostic, outside the timed
+        # steps): one whole PIC_MOM_GAUSS_RES call -- node charge, filter
+        # passes, FP64 flux and residual reductions on the device, the scalars
+        # copied to the host -- the second of two calls (the first records the
+        # reference)
+        for _ in range(2):
+            t0 = time.perf_counter()
+            g = s.gauss_residual()
+            res["gauss_diagnostic_ms"] = 1e3 * (time.perf_counter() - t0)
+        res["gauss"] = {k: g[k] for k in ("drift_max", "res_max", "abs_charge_max", "flux_max", "nodes",
+                                          "non_finite")}
+        log(f"[{tag}] Gauss residual diagnostic: {res['gauss_diagnostic_ms']:.2f} ms per call, {res['gauss']}")
     s.close()
     return res
 
@@ -168,6 +210,21 @@ def run_batched(n_runs, steps, warmup, tune_steps, seq):
                particle_steps=ps, runs=len(sims), particles_start=n0, live_end=live, autotuned=dict(picks),
                steps=steps, warmup=warmup)
     log(f"[batched] {steps} steps: {res['value']:.4e} particle-steps/s, {res['ms_per_step']:.3f} ms/step")
+    # a window of the same runs stepped eagerly between HIP events: the push
+    # kernel's duration over all runs, for the roofline of the batched form
+    ew = min(steps, 32)
+    before = [s.counts()["particle_steps"] for s in sims]
+    b.set_timing(True)
+    b.step(ew)
+    st = b.stage_ms()
+    b.set_timing(False)
+    live_mean = [(s.counts()["particle_steps"] - c) / ew for s, c in zip(sims, before)]
+    cells = [d["params"]["nr"] * d["params"]["nth"] for d in runs]
+    res["stage_ms"] = {k: round(v, 5) for k, v in st.items()}
+    res["eager_steps"] = ew
+    res["push_bytes_per_launch"] = sum(PUSH_BYTES["fp32"] * m + CELL_BYTES["fp32"] * c for m, c in zip(live_mean, cells))
+    res["push_kernel"] = f"k_push<float,{sims[0].grid.chunk_ppt or 8}>"
+    log(f"[batched] eager window of {ew} steps: stages {json.dumps(res['stage_ms'])}")
     if seq:
         wall_s, ps_s = 0.0, 0
         for s in sims:
@@ -257,21 +314,40 @@ def oracle_timing(seconds=8.0, max_threads=16):
     return dict(unit="particle-steps/s", kind="oracle", host_threads=allt, rows=rows)
 
 
+def profile_figures(name: str) -> dict:
+    """'key: value' figures of a committed rocprofv3 summary under profiles/,
+    or {} when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- `"):
+            k, v = line[3:].split("`", 1)[0], line.split(":", 1)[1].strip().rstrip(".")
+            vals[k] = v
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return {}
+    return vals
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    # the timed windows span whole sort intervals (32 FP32 steps after 5
-    # warm-up ones hold the sorts of steps 16 and 32; 16 FP64 steps after 2
-    # hold that of step 16), so that the sort weighs in at its real share
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=16)
+    ap.add_argument("--stress-steps", type=int, default=16)
+    ap.add_argument("--parts", type=str, default="fp32,fp64,batched,stress,cpu",
+                    help="comma list of fp32, fp64, batched, stress (the 2048^2 workload in FP32), cpu")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=str, default="4x16")
-    ap.add_argument("--sort-interval", type=int, default=16)
-    ap.add_argument("--ppt", type=int, default=16, help="particles per thread of a push work-group (4, 8, 16)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--tile", type=str, default="4x16")
+    ap.add_argument("--sort-interval", type=int, default=0,
+                    help="steps between sorts; 0 = the largest divisor of the window from 8 to 16, so that every "
+                         "timed window holds whole sort intervals")
+    ap.add_argument("--ppt", type=int, default=16, help="particles per thread of a push work-group (4, 8, 16)")
     ap.add_argument("--batched-runs", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-warmup", type=int, default=50)
@@ -298,6 +374,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is not sharded across "
               f"GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    parts = set(args.parts.split(","))
+    for flag, part in ((args.no_fp64, "fp64"), (args.no_cpu_baseline, "cpu"), (args.no_batched, "batched"),
+                       (args.no_stress, "stress")):
+        if flag:
+            parts.discard(part)
     # the copy is timed through torch, which must initialise the device before
     # the library's own HIP context exists
     copy_gbs = measured_copy_peak()
@@ -305,46 +386,45 @@ def main():
     from paper_1407_1810_amd import workloads as W
     cfg = W.config(2)
     p = cfg["params"]
-    t0 = time.perf_counter()
-    P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
-    n = len(P["x"])
-    log(f"generated {n} particles for {cfg['name']} in {time.perf_counter() - t0:.1f} s")
     tile = tuple(int(v) for v in args.tile.split("x"))
-    for k, name in ((args.steps, "--steps"), (args.fp64_steps, "--fp64-steps")):
-        if args.sort_interval > 0 and k % args.sort_interval:
-            log(f"note: {name} {k} is not a multiple of the sort interval {args.sort_interval}; the timed "
-                f"window does not hold the sort at its steady-state share")
-    r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, args.sort_interval, args.ppt)
-    r64 = None
-    if not args.no_fp64:
-        r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, args.sort_interval, args.ppt)
-    rb = None
-    if not args.no_batched:
-        rb = run_batched(args.batched_runs, args.batched_steps, args.batched_warmup, args.batched_tune_steps, True)
     cells = p["nr"] * p["nth"]
-    push_ms = r32["stage_ms"]["push"]
-    bytes_launch = PUSH_BYTES["fp32"] * r32["mean_live"] + CELL_BYTES["fp32"] * cells
-    achieved = bytes_launch / (push_ms * 1e-3) / 1e9
-    prof = profiled_counters()
-    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
-    # (scaled by a plain copy of known size), valid for this kernel source
-    traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
-    # issue utilisation of the push from the committed counters: VALU busy
-    # fraction and VALU instructions per particle (figures, not a claim of
-    # which unit bounds the kernel)
-    utilisation = None
-    if "valu_busy" in prof:
-        utilisation = {"valu_busy": float(prof["valu_busy"]),
-                       "valu_instr_per_particle": float(prof["valu_instr_per_particle"])}
-    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, P)
+    P = None
+    if parts & {"fp32", "fp64", "cpu"}:
+        t0 = time.perf_counter()
+        P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
+        log(f"generated {len(P['x'])} particles for {cfg['name']} in {time.perf_counter() - t0:.1f} s")
+    n = 2 * cfg["pairs_per_cell"] * cells
+    k32 = args.sort_interval or auto_sort_interval(args.steps)
+    r32 = r64 = rb = rs = None
+    if "fp32" in parts:
+        r32 = run_gpu(cfg, P, "fp32", args.steps, args.warmup, tile, k32, args.ppt)
+    if "fp64" in parts:
+        k64 = args.sort_interval or auto_sort_interval(args.fp64_steps)
+        r64 = run_gpu(cfg, P, "fp64", args.fp64_steps, min(args.warmup, 2), tile, k64, args.ppt)
+    cpu = cpu_baseline(cfg, P) if "cpu" in parts else None
+    del P
+    if "batched" in parts:
+        rb = run_batched(args.batched_runs, args.batched_steps, args.batched_warmup, args.batched_tune_steps, True)
+    if "stress" in parts:
+        c3 = W.config(3)
+        t0 = time.perf_counter()
+        P3 = W.pair_plasma(c3["params"], c3["pairs_per_cell"], c3["theta_T"], c3["weight"], c3["seed"])
+        log(f"generated {len(P3['x'])} particles for {c3['name']} in {time.perf_counter() - t0:.1f} s")
+        k3 = args.sort_interval or auto_sort_interval(args.stress_steps)
+        rs = run_gpu(c3, P3, "fp32", args.stress_steps, args.warmup, tile, k3, args.ppt, gauss=False,
+                     tag="stress fp32")
+        del P3
+        rs["workload"] = c3["name"]
+        rs["particles"] = 2 * c3["pairs_per_cell"] * c3["params"]["nr"] * c3["params"]["nth"]
+        rs["cells"] = c3["params"]["nr"] * c3["params"]["nth"]
     out = {
         "metric": "particle-steps/sec (push+deposit+field), FP32 and batched vs FP64 GPU",
-        "value": r32["value"],
+        "value": r32["value"] if r32 else None,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["ms_per_step"],
+        "ms_per_step": r32["ms_per_step"] if r32 else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -353,22 +433,50 @@ def main():
         "config": {"workload": cfg["name"], "grid": f"{p['nr']}x{p['nth']}", "particles": n,
                    "particles_per_cell": 2 * cfg["pairs_per_cell"], "background": p["bg_kind"],
                    "injection": bool(p["inject"]), "n_filt": p["n_filt"], "absorb_cells": p["absorb_cells"],
-                   "tile": args.tile, "sort_interval": args.sort_interval, "particles_per_thread": args.ppt,
-                   "precision": "fp32"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": f"k_push<float,{args.ppt}>",
-                     "kernel_ms": push_ms, "algorithmic_bytes_per_launch": bytes_launch,
-                     "measured_copy_peak": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "utilisation": utilisation},
-        "stage_ms": {k: round(v, 5) for k, v in r32["stage_ms"].items()},
-        "fp64_gpu": None if r64 is None else {
-            "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
-            "stage_ms": {k: round(v, 5) for k, v in r64["stage_ms"].items()},
-            "fp32_speedup": r32["value"] / r64["value"], "gauss_diagnostic_ms": r64["gauss_diagnostic_ms"]},
-        "gauss_diagnostic_ms": r32["gauss_diagnostic_ms"],
-        "batched_fp32": rb,
-        "cpu_baseline": cpu,
+                   "tile": args.tile, "sort_interval": k32, "particles_per_thread": args.ppt,
+                   "precision": "fp32", "timed_path": "graph replay (pic_step)"},
     }
+    if r32:
+        prof = profile_figures(PROFILE)
+        # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
+        # (scaled by a plain copy of known size), valid for this kernel source
+        traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+        util = None
+        if "valu_busy" in prof:
+            util = {"valu_busy": float(prof["valu_busy"]), "valu_instr_per_particle": float(prof["valu_instr_per_particle"])}
+        bl = PUSH_BYTES["fp32"] * r32["eager_mean_live"] + CELL_BYTES["fp32"] * cells
+        out["roofline"] = roofline(bl, r32["stage_ms"]["push"], f"k_push<float,{args.ppt}>", copy_gbs, traffic, util)
+        out["roofline"]["timed_on"] = "eager window of the same length after the timed steps, HIP events on the context stream"
+        out["stage_ms"] = {k: round(v, 5) for k, v in r32["stage_ms"].items()}
+        out["eager_ms_per_step"] = r32["eager_ms_per_step"]
+        out["gauss_diagnostic_ms"] = r32.get("gauss_diagnostic_ms")
+        out["gauss"] = r32.get("gauss")
+    if r64:
+        prof = profile_figures(PROFILE_FP64)
+        traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+        bl = PUSH_BYTES["fp64"] * r64["eager_mean_live"] + CELL_BYTES["fp64"] * cells
+        out["fp64_gpu"] = {
+            "value": r64["value"], "ms_per_step": r64["ms_per_step"], "steps": args.fp64_steps,
+            "sort_interval": r64["sort_interval"], "stage_ms": {k: round(v, 5) for k, v in r64["stage_ms"].items()},
+            "fp32_speedup": (r32["value"] / r64["value"]) if r32 else None,
+            "gauss_diagnostic_ms": r64.get("gauss_diagnostic_ms"),
+            "roofline": roofline(bl, r64["stage_ms"]["push"], f"k_push<double,{args.ppt}>", copy_gbs, traffic)}
+    if rb:
+        prof = profile_figures(PROFILE_BATCH)
+        traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+        rb["roofline"] = roofline(rb["push_bytes_per_launch"], rb["stage_ms"]["push"], rb["push_kernel"], copy_gbs,
+                                  traffic)
+        out["batched_fp32"] = rb
+    if rs:
+        prof = profile_figures(PROFILE_STRESS)
+        traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+        bl = PUSH_BYTES["fp32"] * rs["eager_mean_live"] + CELL_BYTES["fp32"] * rs["cells"]
+        out["stress_fp32"] = {
+            "workload": rs["workload"], "particles": rs["particles"], "value": rs["value"],
+            "ms_per_step": rs["ms_per_step"], "steps": args.stress_steps, "sort_interval": rs["sort_interval"],
+            "stage_ms": {k: round(v, 5) for k, v in rs["stage_ms"].items()},
+            "roofline": roofline(bl, rs["stage_ms"]["push"], f"k_push<float,{args.ppt}>", copy_gbs, traffic)}
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -159,6 +159,17 @@ pic_status pic_set_field(pic_ctx *ctx, int32_t comp, const double *host, int64_t
 pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, double *ut, double *up,
                              double *w, uint64_t *id, int64_t cap, int64_t *n_out);
 
+/* The positions of the same particles, in the same order, exactly as stored
+ * (Sec. 3.3 particle state; the int32 cell and the in-cell offsets of the
+ * context's precision, converted to FP64 without rounding): radial and
+ * meridional cell index ci, cj, and offsets fx = x - ci in [0, 1), fy =
+ * y - cj in [0, 1] (1 only in the last meridional cell, at the pole).  An
+ * FP64 absolute coordinate rounds the offset of a particle at cell index N
+ * to about 1e-16 N; these do not.  Any output pointer may be NULL; cap and
+ * n_out as for pic_get_particles. */
+pic_status pic_get_particle_cells(pic_ctx *ctx, int32_t *ci, int32_t *cj, double *fx, double *fy, int64_t cap,
+                                  int64_t *n_out);
+
 /* Moments and diagnostics:
  *  PIC_MOM_COUNTS: out[0..4] = live particles, injected total, deleted
  *                  total, step index, particle-steps advanced since init;

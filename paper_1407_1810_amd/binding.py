@@ -32,7 +32,7 @@ STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "
           -5: "PIC_ENAN", -6: "PIC_EDEVICE", -7: "PIC_ESTATE"}
 
 EXPORTED = ["pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
-            "pic_set_field", "pic_get_particles", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
+            "pic_set_field", "pic_get_particles", "pic_get_particle_cells", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
             "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_save", "pic_load", "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing",
             "pic_batch_stage_ms", "pic_batch_last_error", "pic_batch_destroy"]
@@ -79,6 +79,7 @@ def lib():
         L.pic_get_field.argtypes = [vp, i32, P(d), i64]
         L.pic_set_field.argtypes = [vp, i32, P(d), i64]
         L.pic_get_particles.argtypes = [vp] + [P(d)] * 6 + [P(u64), i64, P(i64)]
+        L.pic_get_particle_cells.argtypes = [vp, P(i32), P(i32), P(d), P(d), i64, P(i64)]
         L.pic_get_moments.argtypes = [vp, i32, P(d), i64]
         L.pic_set_step_index.argtypes = [vp, i64]
         L.pic_set_carry.argtypes = [vp, P(d), i64]
@@ -99,7 +100,8 @@ def lib():
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [vp]
         for name in ("pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape",
-                     "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_moments",
+                     "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_particle_cells",
+                     "pic_get_moments",
                      "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_set_sort", "pic_autotune",
                      "pic_batch_create",
                      "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing", "pic_batch_stage_ms"):
@@ -213,6 +215,17 @@ class Sim:
                                             _up(ids), n, C.byref(got)))
         out["id"] = ids
         return out
+
+    def particle_cells(self):
+        """Cell indices and in-cell offsets of the live particles, exactly as
+        stored, in the order of particles()."""
+        n = int(self.counts()["live"])
+        ci, cj = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
+        fx, fy = np.zeros(n), np.zeros(n)
+        got = C.c_int64()
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        self._check(lib().pic_get_particle_cells(self._h, ip(ci), ip(cj), _dp(fx), _dp(fy), n, C.byref(got)))
+        return dict(ci=ci, cj=cj, fx=fx, fy=fy)
 
     # stepping ----------------------------------------------------------------
     def step(self, n=1):

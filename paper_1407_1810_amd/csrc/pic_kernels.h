@@ -17,12 +17,12 @@
 //  k_push ......... gather + Vay/Boris push + move + VB deposit, one
 //                   work-group per chunk of cell-sorted particles, fields and
 //                   face charges staged in LDS for the chunk's bounding box
-//  k_filter ....... one 1-2-1 pass with the polar remap (App. B)
+//  k_filter ....... the n_filt 1-2-1 passes with the polar remap (App. B),
+//                   staged in LDS per tile
 //  k_ampere ....... Ampere update of E with the filtered face charges, polar
 //                   caps (eq. (erpolarupdate)), walls, lossy layer on E
-//  k_absorb_b ..... lossy layer on B (eq. (EBcond))
-//  k_inject ....... surface pair injection (Sec. 5.3, eq. (volinjeq)), then
-//                   the step index advances
+//  k_close ........ surface pair injection (Sec. 5.3, eq. (volinjeq)), then
+//                   the step index advances; lossy layer on B (eq. (EBcond))
 //  k_node_charge,
 //  k_gauss_flux,
 //  k_gauss_final .. FP64 Gauss diagnostic: node charge, residual, reductions
@@ -33,30 +33,33 @@
 
 namespace pic {
 
-// Per-run metric tables, FP64 on the host, stored as T on the device.
-// Row tables are indexed by the radial node / half index, column tables by
-// the meridional one; see Engine::build_tables for their definitions.
-template <typename T>
+// Per-run metric tables of the field update: the area and length elements
+// of App. A eq. (linearea) factored into radial and meridional tables,
+// formed in FP64 on the host and kept in FP64 on the device whatever the
+// precision of the fields, so that the FP32 field kernels multiply by the
+// stretch metric and the near-axis and polar-cap area factors in FP64 and
+// round the updated field once.  Row tables are indexed by the radial node
+// / half index, column tables by the meridional one; see
+// Engine::build_tables for their definitions.
 struct Metric {
-    const T *r_node;  // r(i), i = -G..nr+G at [i + G]
-    const T *rb;      // r(i + 1/2), i = -G..nr+G at [i + G]
-    const T *invr;    // 1 / r_i
-    const T *idr2;    // 2 / (r_{i+1}^2 - r_i^2)
-    const T *dr;      // r_{i+1} - r_i
-    const T *invrb;   // 1 / rbar_i
-    const T *invA;    // 1 / (2 pi rbar_i^2)
-    const T *idrb2;   // 2 / (rbar_i^2 - rbar_{i-1}^2)
-    const T *drb;     // rbar_i - rbar_{i-1}
-    const T *s;       // sin theta_j
-    const T *k;       // cos theta_j
-    const T *sb;      // sin thetabar_j
-    const T *icBr;    // 1 / (cos theta_j - cos theta_{j+1})
-    const T *idth;    // 1 / (theta_{j+1} - theta_j)
-    const T *idkb;    // 1 / (cos thetabar_{j-1} - cos thetabar_j), caps at the poles
-    const T *isb2pi;  // 1 / (2 pi sin thetabar_j)
-    const T *idthb;   // 1 / (thetabar_j - thetabar_{j-1})
-    const T *ab_int;  // lossy-layer factor at rho = i
-    const T *ab_half; // lossy-layer factor at rho = i + 1/2
+    const double *r_node;  // r(i), i = -G..nr+G at [i + G]
+    const double *rb;      // r(i + 1/2), i = -G..nr+G at [i + G]
+    const double *invr;    // 1 / r_i
+    const double *idr2;    // 2 / (r_{i+1}^2 - r_i^2)
+    const double *dr;      // r_{i+1} - r_i
+    const double *invrb;   // 1 / rbar_i
+    const double *invA;    // 1 / (2 pi rbar_i^2)
+    const double *idrb2;   // 2 / (rbar_i^2 - rbar_{i-1}^2)
+    const double *drb;     // rbar_i - rbar_{i-1}
+    const double *s;       // sin theta_j
+    const double *sb;      // sin thetabar_j
+    const double *icBr;    // 1 / (cos theta_j - cos theta_{j+1})
+    const double *idth;    // 1 / (theta_{j+1} - theta_j)
+    const double *idkb;    // 1 / (cos thetabar_{j-1} - cos thetabar_j), caps at the poles
+    const double *isb2pi;  // 1 / (2 pi sin thetabar_j)
+    const double *idthb;   // 1 / (thetabar_j - thetabar_{j-1})
+    const double *ab_int;  // lossy-layer factor at rho = i
+    const double *ab_half; // lossy-layer factor at rho = i + 1/2
 };
 
 // Device counters of a run (unsigned long long each).
@@ -90,6 +93,12 @@ struct TileMap {
     }
 };
 
+// One span of a sort that holds a key: its index among the run's spans and
+// a particle count (see kSpanList).
+struct SpanEnt {
+    unsigned int s, c;
+};
+
 // Everything the kernels need to know about one run.  The host fills it
 // once (and again when particles with a larger weight arrive); what changes
 // from step to step lives in the counters `ctr`.
@@ -99,7 +108,8 @@ struct RunDev {
     T *fld[9];            // E_r, E_th, E_ph, B_r, B_th, B_ph, F_r, F_th, F_ph
     T *ftmp[3];           // second set of face-charge planes (filter ping-pong)
     const T *ffin[3];     // where the filtered face charges end up after n_filt passes
-    Metric<T> m;
+    Metric m;
+    const T *r_push;      // r(i) at [i + G] in the context's precision: the push's start radii
     Background bg;
     int r_kind, th_kind, mover, n_filt, absorb_cells;
     T c, dxi, inv_dxi, nth_f, two_over_nth, pi_over_nth, inv_pi_over_nth, eps0;
@@ -116,6 +126,9 @@ struct RunDev {
     int sort_interval;    // <= 0: never
     unsigned int *counts, *cursor;
     unsigned long long *offsets;
+    unsigned int *nspan;  // spans of the current sort that hold each key (kSpanOverflow: too many)
+    SpanEnt *slist;       // per key, kSpanList entries (span index, particles there)
+    unsigned int *sbefore; // per entry of slist: the key's particles in the spans before that one
     int inject;
     const double *kn, *sn, *Aj; // cos / sin theta_j, dual face area of node j on the inner conductor
     double rb0, f_inj, q_inj;
@@ -152,6 +165,18 @@ __device__ inline int run_of(const unsigned long long *__restrict__ off, int n_r
     return lo;
 }
 
+// The work-groups of a launch are dealt to the eight XCDs in turn (work-group
+// b runs on XCD b % 8), and each XCD has its own L2.  Field kernels read the
+// rows and columns next to their own tile, so a launch is renumbered to give
+// each XCD a contiguous range of the tiles: neighbouring tiles then share an
+// L2 and the shared rows are fetched from HBM once.  A bijection of
+// [0, g): XCD x takes g / 8 (plus one for the first g % 8) consecutive tiles.
+__device__ __forceinline__ int xcd_tile(int b, int g)
+{
+    const int x = b & 7, k = b >> 3, per = g >> 3, rem = g & 7;
+    return x * per + min(x, rem) + k;
+}
+
 // Field kernels use 64 x 4 work-groups; each thread takes RS consecutive
 // rows of one column, so a work-group covers 64 columns x 4 RS rows, the
 // per-work-group run lookup is paid once per RS cells of a thread, and a
@@ -167,11 +192,16 @@ struct Cell2 {
     int i, j;
 };
 template <int RS>
-__device__ inline Cell2 block_cell(int lb, int ncol)
+__device__ inline Cell2 block_cell(int lb, int ncol, int tx, int ty)
 {
     const int nbx = (ncol + 63) / 64;
     const int by = lb / nbx, bx = lb - by * nbx;
-    return Cell2{by * 4 * RS + RS * (int)threadIdx.y, bx * 64 + (int)threadIdx.x};
+    return Cell2{by * 4 * RS + RS * ty, bx * 64 + tx};
+}
+template <int RS>
+__device__ inline Cell2 block_cell(int lb, int ncol)
+{
+    return block_cell<RS>(lb, ncol, (int)threadIdx.x, (int)threadIdx.y);
 }
 
 template <typename T>
@@ -285,36 +315,36 @@ __global__ __launch_bounds__(256) void k_open(const RunDev<T> *__restrict__ runs
 template <typename T>
 __device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr<const T> __restrict__ Eth,
                                              gptr<const T> __restrict__ Eph, gptr<T> __restrict__ Br,
-                                             gptr<T> __restrict__ Bth, gptr<T> __restrict__ Bph, const Metric<T> &m,
-                                             const Layout &L, int i0, int j, T hc)
+                                             gptr<T> __restrict__ Bth, gptr<T> __restrict__ Bph, const Metric &m,
+                                             const Layout &L, int i0, int j, double hc)
 {
     const int nr = L.nr, nth = L.nth;
-    const gptr<const T> s = glb(m.s), invr = glb(m.invr), icBr = glb(m.icBr), rn = glb(m.r_node),
-                        idr2 = glb(m.idr2), dr = glb(m.dr), idth = glb(m.idth);
-    T br[kFieldRows], bth[kFieldRows], bph[kFieldRows];
+    const gptr<const double> s = glb(m.s), invr = glb(m.invr), icBr = glb(m.icBr), rn = glb(m.r_node),
+                             idr2 = glb(m.idr2), dr = glb(m.dr), idth = glb(m.idth);
+    double br[kFieldRows], bth[kFieldRows], bph[kFieldRows];
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = min(i0 + rs, nr);
         {
-            const T circ = Eph[L.at(i, j)] * s[j] - Eph[L.at(i, j + 1)] * s[min(j + 1, nth)];
-            br[rs] = Br[L.at(i, j)] + hc * circ * invr[i] * icBr[j];
+            const double circ = (double)Eph[L.at(i, j)] * s[j] - (double)Eph[L.at(i, j + 1)] * s[min(j + 1, nth)];
+            br[rs] = (double)Br[L.at(i, j)] + hc * circ * invr[i] * icBr[j];
         }
         {
-            const T circ = Eph[L.at(i + 1, j)] * rn[i + 1 + L.G] - Eph[L.at(i, j)] * rn[i + L.G];
-            bth[rs] = Bth[L.at(i, j)] + hc * circ * idr2[i];
+            const double circ = (double)Eph[L.at(i + 1, j)] * rn[i + 1 + L.G] - (double)Eph[L.at(i, j)] * rn[i + L.G];
+            bth[rs] = (double)Bth[L.at(i, j)] + hc * circ * idr2[i];
         }
         {
-            const T a = Eth[L.at(i, j)] * rn[i + L.G] - Eth[L.at(i + 1, j)] * rn[i + 1 + L.G];
-            const T b = (Er[L.at(i, j)] - Er[L.at(i, j + 1)]) * dr[i] * idth[j];
-            bph[rs] = Bph[L.at(i, j)] + hc * (a - b) * idr2[i];
+            const double a = (double)Eth[L.at(i, j)] * rn[i + L.G] - (double)Eth[L.at(i + 1, j)] * rn[i + 1 + L.G];
+            const double b = ((double)Er[L.at(i, j)] - (double)Er[L.at(i, j + 1)]) * dr[i] * idth[j];
+            bph[rs] = (double)Bph[L.at(i, j)] + hc * (a - b) * idr2[i];
         }
     }
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
-        if (i >= 1 && i < nr && j < nth) Br[L.at(i, j)] = br[rs];
-        if (i < nr && j >= 1 && j < nth) Bth[L.at(i, j)] = bth[rs];
-        if (i < nr && j < nth) Bph[L.at(i, j)] = bph[rs];
+        if (i >= 1 && i < nr && j < nth) Br[L.at(i, j)] = (T)br[rs];
+        if (i < nr && j >= 1 && j < nth) Bth[L.at(i, j)] = (T)bth[rs];
+        if (i < nr && j < nth) Bph[L.at(i, j)] = (T)bph[rs];
     }
 }
 
@@ -325,12 +355,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ runs, int n_runs,
                                                  const int *__restrict__ off, T hc_frac)
 {
-    const int r = run_of(off, n_runs, blockIdx.x);
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = run_of(off, n_runs, b);
     const RunDev<T> &R = runs[r];
-    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], R.L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(b - off[r], R.L.nth + 1);
     if (q.j > R.L.nth) return;
     faraday_rows<T>(glb((const T *)R.fld[cER]), glb((const T *)R.fld[cETH]), glb((const T *)R.fld[cEPH]),
-                    glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j, hc_frac * R.c);
+                    glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j,
+                    (double)hc_frac * R.cd);
 }
 
 // E += (c circulation(B) - F) / area, then the lossy-layer factor on E;
@@ -340,41 +372,41 @@ __device__ __forceinline__ void ampere_rows(gptr<const T> __restrict__ Br, gptr<
                                             gptr<const T> __restrict__ Bph, gptr<const T> __restrict__ Fr,
                                             gptr<const T> __restrict__ Fth, gptr<const T> __restrict__ Fph,
                                             gptr<T> __restrict__ Er, gptr<T> __restrict__ Eth,
-                                            gptr<T> __restrict__ Eph, const Metric<T> &m, const Layout &L, int i0,
-                                            int j, T c)
+                                            gptr<T> __restrict__ Eph, const Metric &m, const Layout &L, int i0,
+                                            int j, double c)
 {
     const int nr = L.nr, nth = L.nth;
-    const gptr<const T> sb = glb(m.sb), invrb = glb(m.invrb), invA = glb(m.invA), idkb = glb(m.idkb),
-                        ab_half = glb(m.ab_half), rb = glb(m.rb), isb2pi = glb(m.isb2pi), idrb2 = glb(m.idrb2),
-                        ab_int = glb(m.ab_int), drb = glb(m.drb), idthb = glb(m.idthb);
-    T er[kFieldRows], eth[kFieldRows], eph[kFieldRows];
-    const T sbj = sb[j], sbw = sb[max(j - 1, 0)];
+    const gptr<const double> sb = glb(m.sb), invrb = glb(m.invrb), invA = glb(m.invA), idkb = glb(m.idkb),
+                             ab_half = glb(m.ab_half), rb = glb(m.rb), isb2pi = glb(m.isb2pi),
+                             idrb2 = glb(m.idrb2), ab_int = glb(m.ab_int), drb = glb(m.drb), idthb = glb(m.idthb);
+    double er[kFieldRows], eth[kFieldRows], eph[kFieldRows];
+    const double sbj = sb[j], sbw = sb[max(j - 1, 0)];
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = min(i0 + rs, nr);
         const size_t e = L.at(i, j);
-        const T bph = Bph[e], bph_w = Bph[L.at(i, j - 1)]; // column -1 lies in the previous row
+        const double bph = Bph[e], bph_w = Bph[L.at(i, j - 1)]; // column -1 lies in the previous row
         {
-            const T t1 = j < nth ? sbj * bph : (T)0;
-            const T t0 = j > 0 ? sbw * bph_w : (T)0;
-            er[rs] = (Er[e] + (c * (t1 - t0) * invrb[i] - Fr[e] * invA[i]) * idkb[j]) * ab_half[i];
+            const double t1 = j < nth ? sbj * bph : 0.0;
+            const double t0 = j > 0 ? sbw * bph_w : 0.0;
+            er[rs] = ((double)Er[e] + (c * (t1 - t0) * invrb[i] - (double)Fr[e] * invA[i]) * idkb[j]) * ab_half[i];
         }
         {
-            const T circ = rb[i - 1 + L.G] * Bph[L.at(i - 1, j)] - rb[i + L.G] * bph;
-            eth[rs] = (Eth[e] + (c * circ - Fth[e] * isb2pi[j]) * idrb2[i]) * ab_int[i];
+            const double circ = rb[i - 1 + L.G] * (double)Bph[L.at(i - 1, j)] - rb[i + L.G] * bph;
+            eth[rs] = ((double)Eth[e] + (c * circ - (double)Fth[e] * isb2pi[j]) * idrb2[i]) * ab_int[i];
         }
         {
-            const T a = rb[i + L.G] * Bth[e] - rb[i - 1 + L.G] * Bth[L.at(i - 1, j)];
-            const T b = (Br[e] - Br[L.at(i, j - 1)]) * drb[i] * idthb[j];
-            eph[rs] = (Eph[e] + (c * (a - b) - Fph[e] * idthb[j]) * idrb2[i]) * ab_int[i];
+            const double a = rb[i + L.G] * (double)Bth[e] - rb[i - 1 + L.G] * (double)Bth[L.at(i - 1, j)];
+            const double b = ((double)Br[e] - (double)Br[L.at(i, j - 1)]) * drb[i] * idthb[j];
+            eph[rs] = ((double)Eph[e] + (c * (a - b) - (double)Fph[e] * idthb[j]) * idrb2[i]) * ab_int[i];
         }
     }
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = i0 + rs;
-        if (i < nr) Er[L.at(i, j)] = er[rs];
-        if (i >= 1 && i < nr && j < nth) Eth[L.at(i, j)] = eth[rs];
-        if (i >= 1 && i < nr && j >= 1 && j < nth) Eph[L.at(i, j)] = eph[rs];
+        if (i < nr) Er[L.at(i, j)] = (T)er[rs];
+        if (i >= 1 && i < nr && j < nth) Eth[L.at(i, j)] = (T)eth[rs];
+        if (i >= 1 && i < nr && j >= 1 && j < nth) Eph[L.at(i, j)] = (T)eph[rs];
     }
 }
 
@@ -382,28 +414,27 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_ampere(const RunDev<T> *__restrict__ runs, int n_runs,
                                                 const int *__restrict__ off)
 {
-    const int r = run_of(off, n_runs, blockIdx.x);
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = run_of(off, n_runs, b);
     const RunDev<T> &R = runs[r];
-    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], R.L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(b - off[r], R.L.nth + 1);
     if (q.j > R.L.nth) return;
     ampere_rows<T>(glb((const T *)R.fld[cBR]), glb((const T *)R.fld[cBTH]), glb((const T *)R.fld[cBPH]),
                    glb(R.ffin[0]), glb(R.ffin[1]), glb(R.ffin[2]), glb(R.fld[cER]), glb(R.fld[cETH]),
-                   glb(R.fld[cEPH]), R.m, R.L, q.i, q.j, R.c);
+                   glb(R.fld[cEPH]), R.m, R.L, q.i, q.j, R.cd);
 }
 
-// Lossy layer on B over rows nr - absorb_cells - 1 .. nr (the factor is 1
-// below); runs without a layer own no work-groups.
+// Lossy layer on B (eq. (EBcond)) over rows nr - absorb_cells - 1 .. nr
+// (the factor is 1 below), for one 64 x 4 block of threads: thread (tx, ty)
+// of block lb of run R, kFieldRows rows each.
 template <typename T>
-__global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ runs, int n_runs,
-                                                  const int *__restrict__ off)
+__device__ inline void absorb_b_block(const RunDev<T> &R, int lb, int tx, int ty)
 {
-    const int r = run_of(off, n_runs, blockIdx.x);
-    const RunDev<T> &R = runs[r];
     const Layout L = R.L;
-    const Cell2 q = block_cell<kFieldRows>(blockIdx.x - off[r], L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(lb, L.nth + 1, tx, ty);
     const int j = q.j;
     if (j > L.nth) return;
-    const gptr<const T> ab_int = glb(R.m.ab_int), ab_half = glb(R.m.ab_half);
+    const gptr<const double> ab_int = glb(R.m.ab_int), ab_half = glb(R.m.ab_half);
     const gptr<T> Br = glb(R.fld[cBR]), Bth = glb(R.fld[cBTH]), Bph = glb(R.fld[cBPH]);
     const int i0 = L.nr - R.absorb_cells - 1 + q.i;
     // all loads of the thread's rows (unconditional, at a row clamped into
@@ -412,9 +443,9 @@ __global__ __launch_bounds__(256) void k_absorb_b(const RunDev<T> *__restrict__ 
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
         const int i = min(max(i0 + rs, 0), L.nr);
-        br[rs] = Br[L.at(i, j)] * ab_int[i];
-        bth[rs] = Bth[L.at(i, j)] * ab_half[i];
-        bph[rs] = Bph[L.at(i, j)] * ab_half[i];
+        br[rs] = (T)((double)Br[L.at(i, j)] * ab_int[i]);
+        bth[rs] = (T)((double)Bth[L.at(i, j)] * ab_half[i]);
+        bph[rs] = (T)((double)Bph[L.at(i, j)] * ab_half[i]);
     }
 #pragma unroll
     for (int rs = 0; rs < kFieldRows; ++rs) {
@@ -471,7 +502,8 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     static_assert(kFiltTR * kFiltTC % 256 == 0, "the filter tile is a whole number of 256-entry sweeps");
     static_assert(3 * N * sizeof(T) <= 65536, "the filter's LDS arrays fit in 64 KB");
     __shared__ T sa[N], sb[N], st[N];
-    const int r = run_of(off, n_runs, blockIdx.x);
+    const int bt = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = run_of(off, n_runs, bt);
     const RunDev<T> &R = runs[r];
     const int passes = R.n_filt;
     const Layout L = R.L;
@@ -479,7 +511,7 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
     const int kind = comp == 1 ? 1 : 0;
     const int nth = L.nth, ncol = kind ? nth : nth + 1;
     const int first = -L.G, last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
-    const int lb = blockIdx.x - off[r];
+    const int lb = bt - off[r];
     const int nbx = (nth + 1 + kFiltTC - 1) / kFiltTC;
     const int by = lb / nbx, bx = lb - by * nbx;
     const int i0 = first + by * kFiltTR - H, j0 = bx * kFiltTC - H; // entry (0, 0) of the tile
@@ -616,7 +648,7 @@ __device__ inline PushArgs<T> push_args(const RunDev<T> &R, int cur, double step
     p.inv_pi_over_nth = R.inv_pi_over_nth;
     p.eps0 = R.eps0;
     p.inv_rl = (T)inv_light_cylinder(R.omega, R.t_spin, R.cd, step);
-    p.r_node = glb(R.m.r_node);
+    p.r_node = glb(R.r_push);
     p.cell = glb(R.cell[cur]);
     p.dx = glb(R.arr[cur][0]);
     p.dy = glb(R.arr[cur][1]);
@@ -1348,11 +1380,32 @@ __global__ __launch_bounds__(256, push_waves<T>()) void k_push(const RunDev<T> *
 constexpr int kInjMaxPer = 8; // nth + 1 <= 8192
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_inject(const RunDev<T> *__restrict__ runs)
+__device__ void inject_run(const RunDev<T> &R);
+
+// The step's closing kernel (it runs after the Ampere update, which reads
+// the B that the lossy layer then damps): work-group r < n_runs injects the
+// pairs of run r and advances its step index; the other work-groups apply
+// the lossy layer to B, four 64 x 4 blocks of the layer map `off` each.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_close(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                const int *__restrict__ off)
+{
+    if ((int)blockIdx.x < n_runs) {
+        inject_run(runs[blockIdx.x]);
+        return;
+    }
+    const int sub = (int)threadIdx.x >> 8, t = (int)threadIdx.x & 255;
+    const int b = ((int)blockIdx.x - n_runs) * 4 + sub;
+    if (b >= off[n_runs]) return;
+    const int r = run_of(off, n_runs, b);
+    absorb_b_block(runs[r], b - off[r], t & 63, t >> 6);
+}
+
+template <typename T>
+__device__ void inject_run(const RunDev<T> &R)
 {
     __shared__ long long wsum[16];
     __shared__ int ok;
-    const RunDev<T> &R = runs[blockIdx.x];
     const gptr<unsigned long long> ctr = glb(R.ctr);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t step = ctr[kStep];
@@ -1491,6 +1544,20 @@ constexpr int kSortPer = kSortSpan / 256;
 // counter directly.
 constexpr int kSortWin = 4096;
 
+// A key held by at most kSpanList spans of a sort is placed span by span in
+// span order, so that the sort is stable: every particle keeps the order of
+// its key's particles in storage.  The histogram records, per key, the spans
+// that hold it and their counts, and the scan orders each key's spans and
+// turns the counts into the key's particles in the spans before each.
+// Between sorts particles move a few cells, so a key's particles lie in its
+// own spans and in those of the tiles around it: with a key's particles in
+// at most three spans, nine tiles hold at most 27.  A key held by more spans
+// (an unsorted store: the first sort of particles loaded in any order), or
+// met outside a span's LDS window, is placed in the order the spans claim
+// it, and the sort is stable only within each span.
+constexpr int kSpanList = 32;
+constexpr unsigned int kSpanOverflow = 1u << 20;
+
 __device__ __forceinline__ int sort_window_base(int first_key)
 {
     return first_key > kSortWin / 2 ? first_key - kSortWin / 2 : 0;
@@ -1530,6 +1597,7 @@ __global__ __launch_bounds__(256) void k_sort_zero(const RunDev<T> *__restrict__
     if (e <= R.tm.n_keys) {
         glb(R.counts)[e] = 0;
         glb(R.cursor)[e] = 0;
+        glb(R.nspan)[e] = 0;
     }
 }
 
@@ -1562,6 +1630,9 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
             cw[u] = k < ns ? cs[k] : kDead;
         }
         const int base = sort_window_base(tm.key(cs[0]));
+        const gptr<unsigned int> nspan = glb(R.nspan);
+        SpanEnt *const slist = R.slist; // struct copies need generic pointers
+        const unsigned int sidx = (unsigned int)(gs - span_off[r]);
         __syncthreads(); // the window is clear
 #pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
@@ -1569,15 +1640,22 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
             const KeyRun kr = key_run(key, tid & 63);
             if (kr.head && key != INT_MAX) {
                 const unsigned int dw = (unsigned int)(key - base);
-                if (dw < (unsigned int)kSortWin) atomicAdd(&h[dw], (unsigned int)kr.len);
-                else atomic_add(counts + key, (unsigned int)kr.len);
+                if (dw < (unsigned int)kSortWin) {
+                    atomicAdd(&h[dw], (unsigned int)kr.len);
+                } else {
+                    atomic_add(counts + key, (unsigned int)kr.len);
+                    atomic_add(nspan + key, kSpanOverflow);
+                }
             }
         }
         __syncthreads();
         for (int e = tid; e < kSortWin; e += 256) {
             const unsigned int v = h[e];
             if (v) {
-                atomic_add(counts + base + e, v);
+                const int key = base + e;
+                atomic_add(counts + key, v);
+                const unsigned int slot = atomic_add_fetch_old(nspan + key, 1u);
+                if (slot < (unsigned int)kSpanList) slist[(size_t)key * kSpanList + slot] = SpanEnt{sidx, v};
                 h[e] = 0;
             }
         }
@@ -1619,34 +1697,80 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const RunDev<T> *__restrict_
     if (tid == 0) ctr[kLive] = s[1023] - counts[n_keys];
 }
 
-// Scatter into the other buffer.  Per span: each particle takes its rank
-// among the span's particles of its key from an LDS atomic (one per run of
-// equal keys in a wave); each key present claims its slots with one global
-// atomic on its cursor; the particles are then copied, 4 per thread at a
-// time, to offsets[key] + claim + rank.  The order of equal keys is kept
-// within a wave's 64 particles, not across the waves of a span.  Deleted particles (the
-// last key) are dropped; lanes without a particle write a spare slot past
-// the capacity, so that every lane stores.
+// Per key held by at most kSpanList spans: for each of its spans, the
+// key's particles in the spans before it (a lower span index), so that the
+// scatter places the key span by span in span order.  One thread per key
+// (the key map of the sort's zeroing), entries compared all against all:
+// a key is held by a few spans, and no order of the list is needed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sort_spans(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                    const int *__restrict__ off)
+{
+    const int r = run_of(off, n_runs, blockIdx.x);
+    const RunDev<T> &R = runs[r];
+    if (!glb(R.ctr)[kSortNow]) return;
+    const int q = (blockIdx.x - off[r]) * 256 + threadIdx.x;
+    if (q > R.tm.n_keys) return;
+    const unsigned int m = glb((const unsigned int *)R.nspan)[q];
+    if (m > (unsigned int)kSpanList) return;
+    const SpanEnt *const a = R.slist + (size_t)q * kSpanList; // struct copies need generic pointers
+    const gptr<unsigned int> before = glb(R.sbefore) + (size_t)q * kSpanList;
+    for (unsigned int k = 0; k < m; ++k) {
+        const unsigned int sk = a[k].s;
+        unsigned int b = 0;
+        for (unsigned int l = 0; l < m; ++l) {
+            const SpanEnt e = a[l];
+            if (e.s < sk) b += e.c;
+        }
+        before[k] = b;
+    }
+}
+
+// Scatter into the other buffer.  Per span, in window of tile keys: each
+// particle's rank among the span's particles of its key in storage order --
+// the particles of the keys earlier in the span (a running count per key in
+// LDS), of the earlier waves for the same slice of 256 (a list of (key,
+// count) per wave), and of the earlier lanes of its own wave (a ballot per
+// distinct key) -- so that the ranks do not depend on the order in which
+// waves run.  Each key present then takes its block of slots: from the
+// key's span list (the key's particles in the spans before this one) when
+// the key is listed, else by a claim on the key's cursor; a key outside the
+// window is claimed by runs of equal keys in a wave, on its cursor.  The
+// particles are then copied, 4 per thread at a time, to offsets[key] +
+// block + rank.  Deleted particles (the last key) are dropped; lanes without
+// a particle write a spare slot past the capacity, so that every lane
+// stores.
+__device__ inline unsigned long long lanemask_lt(int lane)
+{
+    return lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restrict__ runs, int n_runs,
                                                       const unsigned long long *__restrict__ span_off)
 {
     __shared__ unsigned int h[kSortWin];
-    const int tid = threadIdx.x;
+    __shared__ int2 wl[4][64]; // per wave: (key in the window, particles) of the current slice
+    __shared__ int nwl[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
-    const unsigned long long nspan = span_off[n_runs];
-    for (unsigned long long gs = blockIdx.x; gs < nspan; gs += gridDim.x) {
+    const unsigned long long nspan_all = span_off[n_runs];
+    for (unsigned long long gs = blockIdx.x; gs < nspan_all; gs += gridDim.x) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
         const RunDev<T> &R = runs[r];
         const gptr<const unsigned long long> ctr = glb((const unsigned long long *)R.ctr);
         const unsigned long long n = ctr[kTotal];
         const int cur = (int)ctr[kCur], nxt = cur ^ 1;
         const TileMap tm = R.tm;
-        const unsigned long long s0 = (gs - span_off[r]) * kSortSpan;
+        const unsigned int sidx = (unsigned int)(gs - span_off[r]);
+        const unsigned long long s0 = (unsigned long long)sidx * kSortSpan;
         const uint32_t ns = (uint32_t)min(n - s0, (unsigned long long)kSortSpan);
         const gptr<const uint32_t> cs = glb((const uint32_t *)R.cell[cur]) + s0;
         const gptr<const unsigned long long> offsets = glb((const unsigned long long *)R.offsets);
         const gptr<unsigned int> cursor = glb(R.cursor);
+        const gptr<const unsigned int> nspan = glb((const unsigned int *)R.nspan);
+        const SpanEnt *const slist = R.slist;
+        const gptr<const unsigned int> sbefore = glb((const unsigned int *)R.sbefore);
         const uint32_t cap = (uint32_t)R.capacity;
         uint32_t cw[kSortPer];
 #pragma unroll
@@ -1656,27 +1780,72 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
         }
         const int base = sort_window_base(tm.key(cs[0]));
         __syncthreads(); // the window is clear
-        // rank within the span among the particles of the same key (in the
-        // window), or the slot itself (outside the window: claimed by run);
-        // one atomic per run of equal keys in a wave, ranks follow lane order
         uint32_t rank[kSortPer];
-#pragma unroll
+#pragma unroll 1
         for (int u = 0; u < kSortPer; ++u) {
             const int key = 256u * u + tid < ns ? tm.key(cw[u]) : INT_MAX;
             const bool live = key != INT_MAX && key != tm.n_keys;
-            const KeyRun kr = key_run(key, tid & 63);
+            const unsigned int dw = (unsigned int)(key - base);
+            const bool inw = live && dw < (unsigned int)kSortWin;
+            // outside the window: one claim per run of equal keys in the wave
+            const KeyRun kr = key_run(key, lane);
             uint32_t got = 0;
-            if (kr.head && live) {
-                const unsigned int dw = (unsigned int)(key - base);
-                if (dw < (unsigned int)kSortWin) got = atomicAdd(&h[dw], (unsigned int)kr.len);
-                else got = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, (unsigned int)kr.len));
+            if (kr.head && live && !inw)
+                got = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, (unsigned int)kr.len));
+            const uint32_t out_rank = (uint32_t)__shfl((int)got, kr.head_lane) + (uint32_t)(lane - kr.head_lane);
+            // inside: the lane's rank among the wave's lanes of its key, and
+            // the wave's (key, count) list, one entry per distinct key
+            unsigned long long pending = __ballot(inw);
+            int nl = 0;
+            uint32_t lrank = 0;
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const int lk = __shfl(key, leader);
+                const unsigned long long m = __ballot(inw && key == lk);
+                if (inw && key == lk) lrank = (uint32_t)__popcll(m & lanemask_lt(lane));
+                if (lane == 0) wl[wv][nl] = make_int2(lk - base, __popcll(m));
+                ++nl;
+                pending &= ~m;
             }
-            rank[u] = (uint32_t)__shfl((int)got, kr.head_lane) + (uint32_t)((tid & 63) - kr.head_lane);
+            if (lane == 0) nwl[wv] = nl;
+            __syncthreads();
+            uint32_t pre = 0;
+            if (inw) {
+                pre = h[dw];
+                for (int w2 = 0; w2 < wv; ++w2) {
+                    const int n2 = nwl[w2];
+                    for (int q = 0; q < n2; ++q) {
+                        const int2 e = wl[w2][q];
+                        if (e.x == (int)dw) pre += (uint32_t)e.y;
+                    }
+                }
+            }
+            rank[u] = inw ? pre + lrank : out_rank;
+            __syncthreads(); // every read of the running counts is done
+            if (lane < nl) {
+                const int2 e = wl[wv][lane];
+                atomicAdd(&h[e.x], (unsigned int)e.y);
+            }
         }
         __syncthreads();
         for (int e = tid; e < kSortWin; e += 256) {
             const unsigned int v = h[e];
-            if (v) h[e] = (unsigned int)(offsets[base + e] + atomic_add_fetch_old(cursor + base + e, v));
+            if (v) {
+                const int key = base + e;
+                const unsigned int m = nspan[key];
+                unsigned long long blk = 0;
+                bool listed = false;
+                if (m <= (unsigned int)kSpanList) {
+                    for (unsigned int q = 0; q < m; ++q) {
+                        if (slist[(size_t)key * kSpanList + q].s == sidx) {
+                            blk = sbefore[(size_t)key * kSpanList + q];
+                            listed = true;
+                        }
+                    }
+                }
+                if (!listed) blk = atomic_add_fetch_old(cursor + key, v);
+                h[e] = (unsigned int)(offsets[key] + blk);
+            }
         }
         __syncthreads();
         uint32_t dest[kSortPer];

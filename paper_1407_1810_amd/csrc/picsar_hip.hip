@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -305,6 +306,7 @@ private:
             k_step_begin<T><<<1, 64, 0, s>>>(runs_, n_, kSortSpan, span_off_, 1);
             if (tot_[kMapKeys] > 0) k_sort_zero<T><<<tot_[kMapKeys], 256, 0, s>>>(runs_, n_, map(kMapKeys));
             k_sort_hist<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
+            if (tot_[kMapKeys] > 0) k_sort_spans<T><<<tot_[kMapKeys], 256, 0, s>>>(runs_, n_, map(kMapKeys));
             k_sort_scan<T><<<n_, 1024, 0, s>>>(runs_);
             k_sort_scatter<T><<<sort_blocks_, 256, 0, s>>>(runs_, n_, span_off_);
             HIPCHK(hipGetLastError());
@@ -341,14 +343,12 @@ private:
         k_ampere<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid));
         HIPCHK(hipGetLastError());
         mark(t, s, kStAmpere, false);
+        // injection and the lossy layer on B in one closing launch (its time
+        // is reported as the injection stage; the absorb stage stays empty)
         mark(t, s, kStAbsorb, true);
-        if (tot_[kMapAbsorb] > 0) {
-            k_absorb_b<T><<<tot_[kMapAbsorb], blk2, 0, s>>>(runs_, n_, map(kMapAbsorb));
-            HIPCHK(hipGetLastError());
-        }
         mark(t, s, kStAbsorb, false);
         mark(t, s, kStInject, true);
-        k_inject<T><<<n_, 1024, 0, s>>>(runs_);
+        k_close<T><<<n_ + (tot_[kMapAbsorb] + 3) / 4, 1024, 0, s>>>(runs_, n_, map(kMapAbsorb));
         HIPCHK(hipGetLastError());
         mark(t, s, kStInject, false);
         mark(t, s, kStTotal, false);
@@ -423,6 +423,7 @@ public:
     virtual void set_field(int comp, const double *in) = 0;
     virtual int64_t get_particles(double *x, double *y, double *ur, double *ut, double *up, double *w,
                                   uint64_t *id, int64_t cap) = 0;
+    virtual int64_t get_cells(int32_t *ci, int32_t *cj, double *fx, double *fy, int64_t cap) = 0;
     virtual void counts(double *out) = 0;
     virtual void gauss(double *out) = 0;
     virtual void gauss_residual(double *out) = 0;
@@ -521,6 +522,7 @@ public:
         }
         build_tables();
         R.m = m_;
+        R.r_push = r_push_;
         R.bg = Background{ph.bg_kind, ph.B0, gd.r_in};
         R.r_kind = gd.r_kind;
         R.th_kind = gd.th_kind;
@@ -599,10 +601,11 @@ public:
     // this run's sort schedule as the host records it (see SortSched)
     SortSched sched() { return SortSched{rd_.sort_interval, &sched_step_, &sched_need_}; }
 
-    void inject(int64_t n, const double *x, const double *y, const double *ur, const double *ut, const double *up,
-                const double *w, const uint64_t *id) override
+    // Checks of an append of n particles from the host (positions inside the
+    // grid, room in the store); returns the first slot they take and the
+    // current buffer, and raises the largest |w| held.
+    unsigned long long inject_begin(int64_t n, const double *x, const double *y, const double *w, int &cur)
     {
-        if (n == 0) return;
         const int nr = gd.nr, nth = gd.nth;
         const double lim = gd.n_filt + 1.0;
         for (int64_t q = 0; q < n; ++q) {
@@ -612,9 +615,44 @@ public:
         unsigned long long c[kNumCounters];
         read_counters(c);
         const unsigned long long ntot = c[kTotal];
-        const int cur = (int)c[kCur];
+        cur = (int)c[kCur];
         if ((int64_t)ntot + n > cap_) throw StatusError{PIC_ECAPACITY, "particle capacity exceeded"};
         for (int64_t q = 0; q < n; ++q) qmax_ = std::max(qmax_, std::fabs(w[q]));
+        return ntot;
+    }
+
+    // Cell + offset conversion of m staged particles (stage: six arrays of m
+    // doubles; sid: m ids or null) into slots at..at+m-1.
+    void inject_load(const double *stage, const uint64_t *sid, int64_t m, unsigned long long at, int cur)
+    {
+        const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
+        k_load<T><<<blocks, 256, 0, stream>>>(stage, sid, m, (long long)at, gd.nth, cell_[cur], arr_[cur][0],
+                                              arr_[cur][1], arr_[cur][2], arr_[cur][3], arr_[cur][4], arr_[cur][5],
+                                              id_[cur]);
+        HIPCHK(hipGetLastError());
+    }
+
+    // The new particle count, a sort at the next step, the deposit scale.
+    void inject_end(int64_t n, unsigned long long ntot)
+    {
+        const unsigned long long upd[2] = {ntot + n, 1ull};
+        HIPCHK(hipMemcpyAsync(ctr_ + kTotal, &upd[0], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(ctr_ + kNeedSort, &upd[1], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        sched_need_ = true;
+        gauss_unref();
+        if (set_dep_scale()) {
+            plan_.upload({rd_}, stream);
+            ++version;
+        }
+    }
+
+    void inject(int64_t n, const double *x, const double *y, const double *ur, const double *ut, const double *up,
+                const double *w, const uint64_t *id) override
+    {
+        if (n == 0) return;
+        int cur = 0;
+        const unsigned long long ntot = inject_begin(n, x, y, w, cur);
         const int64_t chunk = 1 << 22;
         double *stage = dev_alloc<double>(6 * (size_t)std::min(n, chunk));
         uint64_t *sid = id ? dev_alloc<uint64_t>((size_t)std::min(n, chunk)) : nullptr;
@@ -627,11 +665,7 @@ public:
                 for (int a = 0; a < 6; ++a) std::memcpy(&hb[(size_t)a * m], srcs[a] + o, sizeof(double) * m);
                 HIPCHK(hipMemcpyAsync(stage, hb.data(), sizeof(double) * 6 * m, hipMemcpyHostToDevice, stream));
                 if (sid) HIPCHK(hipMemcpyAsync(sid, id + o, sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream));
-                const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
-                k_load<T><<<blocks, 256, 0, stream>>>(stage, sid, m, (long long)(ntot + o), nth, cell_[cur],
-                                                      arr_[cur][0], arr_[cur][1], arr_[cur][2], arr_[cur][3],
-                                                      arr_[cur][4], arr_[cur][5], id_[cur]);
-                HIPCHK(hipGetLastError());
+                inject_load(stage, sid, m, ntot + o, cur);
                 HIPCHK(hipStreamSynchronize(stream));
             }
         } catch (...) {
@@ -643,16 +677,7 @@ public:
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipFree(stage));
         if (sid) HIPCHK(hipFree(sid));
-        const unsigned long long upd[2] = {ntot + n, 1ull};
-        HIPCHK(hipMemcpyAsync(ctr_ + kTotal, &upd[0], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync(ctr_ + kNeedSort, &upd[1], sizeof(unsigned long long), hipMemcpyHostToDevice, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        sched_need_ = true;
-        gauss_unref();
-        if (set_dep_scale()) {
-            plan_.upload({rd_}, stream);
-            ++version;
-        }
+        inject_end(n, ntot);
     }
 
     void step(int n) override
@@ -736,6 +761,38 @@ public:
             int64_t m = 0;
             for (size_t q = 0; q < ntot; ++q)
                 if (hc[q] != kDead) id[m++] = with_ids_ ? hi[q] : (uint64_t)q;
+        }
+        return live;
+    }
+
+    int64_t get_cells(int32_t *ci, int32_t *cj, double *fx, double *fy, int64_t cap) override
+    {
+        unsigned long long c[kNumCounters];
+        read_counters(c);
+        const unsigned long long ntot = c[kTotal];
+        const int cur = (int)c[kCur];
+        std::vector<uint32_t> hc(ntot);
+        HIPCHK(hipMemcpyAsync(hc.data(), cell_[cur], sizeof(uint32_t) * ntot, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        int64_t live = 0;
+        for (auto cl : hc) live += cl != kDead;
+        if (live > cap) return -live;
+        int64_t m = 0;
+        for (size_t q = 0; q < ntot; ++q) {
+            if (hc[q] == kDead) continue;
+            if (ci) ci[m] = cell_i(hc[q]);
+            if (cj) cj[m] = cell_j(hc[q]);
+            ++m;
+        }
+        std::vector<T> ha(ntot);
+        double *outs[2] = {fx, fy};
+        for (int a = 0; a < 2; ++a) {
+            if (!outs[a]) continue;
+            HIPCHK(hipMemcpyAsync(ha.data(), arr_[cur][a], sizeof(T) * ntot, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            m = 0;
+            for (size_t q = 0; q < ntot; ++q)
+                if (hc[q] != kDead) outs[a][m++] = (double)ha[q];
         }
         return live;
     }
@@ -1039,7 +1096,8 @@ private:
     void sort_state(int tile_r, int tile_th, int sort_interval)
     {
         RunDev<T> &R = rd_;
-        for (void *p : {(void *)counts_, (void *)cursor_, (void *)offsets_}) dfree(p);
+        for (void *p : {(void *)counts_, (void *)cursor_, (void *)offsets_, (void *)nspan_, (void *)slist_,
+                        (void *)sbefore_}) dfree(p);
         // sort tiles over rows -G..nr+G
         const int ntr = (L.rows() + tile_r - 1) / tile_r;
         const int ntj = (L.nth + tile_th - 1) / tile_th;
@@ -1048,9 +1106,15 @@ private:
         counts_ = dalloc<unsigned int>(R.tm.n_keys + 1);
         cursor_ = dalloc<unsigned int>(R.tm.n_keys + 1);
         offsets_ = dalloc<unsigned long long>(R.tm.n_keys + 1);
+        nspan_ = dalloc<unsigned int>(R.tm.n_keys + 1);
+        slist_ = dalloc<SpanEnt>((size_t)(R.tm.n_keys + 1) * kSpanList);
+        sbefore_ = dalloc<unsigned int>((size_t)(R.tm.n_keys + 1) * kSpanList);
         R.counts = counts_;
         R.cursor = cursor_;
         R.offsets = offsets_;
+        R.nspan = nspan_;
+        R.slist = slist_;
+        R.sbefore = sbefore_;
         // LDS plane size: a chunk spans at most two neighbouring tiles (serpentine
         // order), widened by the drift since the last sort (at most ~0.7 cell
         // per step in grid units) and the stencil halo (one cell below, two above)
@@ -1073,15 +1137,17 @@ private:
     unsigned long long *ctr_ = nullptr;
     int *status_ = nullptr;
     double *carry_ = nullptr;
-    unsigned int *counts_ = nullptr, *cursor_ = nullptr;
+    unsigned int *counts_ = nullptr, *cursor_ = nullptr, *nspan_ = nullptr;
     unsigned long long *offsets_ = nullptr;
+    SpanEnt *slist_ = nullptr;
+    unsigned int *sbefore_ = nullptr;
     int64_t cap_ = 0;
     uint64_t sched_step_ = 0; // the device's kStep and kNeedSort, as every host action and step sets them
     bool sched_need_ = true;
     double qmax_ = 0.0; // largest |w| held so far: sets the fixed-point deposit scale
     bool with_ids_ = false;
-    Metric<T> m_{};
-    const T *r_node_ = nullptr, *k_node_ = nullptr;
+    Metric m_{};
+    const T *r_push_ = nullptr;
     const double *dkn_ = nullptr, *dsn_ = nullptr, *dAj_ = nullptr;
     const double *gA_r_ = nullptr, *gdkb_ = nullptr, *gA_t_ = nullptr, *gsb_ = nullptr;
     const double *grb_ = nullptr, *gkc_ = nullptr, *gdk_ = nullptr;
@@ -1220,27 +1286,25 @@ private:
             idkb[j] = 1.0 / dkb[j];
             if (j >= 1 && j < nth) idthb[j] = 1.0 / (g.th(j + 0.5) - g.th(j - 0.5));
         }
-        m_.r_node = upload<T>(r_node);
-        m_.rb = upload<T>(rb);
-        m_.invr = upload<T>(invr);
-        m_.idr2 = upload<T>(idr2);
-        m_.dr = upload<T>(dr);
-        m_.invrb = upload<T>(invrb);
-        m_.invA = upload<T>(invA);
-        m_.idrb2 = upload<T>(idrb2);
-        m_.drb = upload<T>(drb);
-        m_.s = upload<T>(s);
-        m_.k = upload<T>(k);
-        m_.sb = upload<T>(sb);
-        m_.icBr = upload<T>(icBr);
-        m_.idth = upload<T>(idth);
-        m_.idkb = upload<T>(idkb);
-        m_.isb2pi = upload<T>(isb2pi);
-        m_.idthb = upload<T>(idthb);
-        m_.ab_int = upload<T>(abi);
-        m_.ab_half = upload<T>(abh);
-        r_node_ = m_.r_node;
-        k_node_ = m_.k;
+        m_.r_node = upload<double>(r_node);
+        m_.rb = upload<double>(rb);
+        m_.invr = upload<double>(invr);
+        m_.idr2 = upload<double>(idr2);
+        m_.dr = upload<double>(dr);
+        m_.invrb = upload<double>(invrb);
+        m_.invA = upload<double>(invA);
+        m_.idrb2 = upload<double>(idrb2);
+        m_.drb = upload<double>(drb);
+        m_.s = upload<double>(s);
+        m_.sb = upload<double>(sb);
+        m_.icBr = upload<double>(icBr);
+        m_.idth = upload<double>(idth);
+        m_.idkb = upload<double>(idkb);
+        m_.isb2pi = upload<double>(isb2pi);
+        m_.idthb = upload<double>(idthb);
+        m_.ab_int = upload<double>(abi);
+        m_.ab_half = upload<double>(abh);
+        r_push_ = upload<T>(r_node);
         // FP64 tables of the injection and the Gauss diagnostic
         std::vector<double> Aj(nth + 1);
         for (int j = 0; j <= nth; ++j) Aj[j] = 2.0 * kPi * gd.r_in * gd.r_in * dkb[j];
@@ -1527,6 +1591,17 @@ pic_status pic_get_particles(pic_ctx *ctx, double *x, double *y, double *ur, dou
     return guarded(ctx, [&] {
         need_engine(ctx);
         const int64_t n = ctx->eng->get_particles(x, y, ur, ut, up, w, id, cap);
+        if (n_out) *n_out = n < 0 ? -n : n;
+        if (n < 0) throw StatusError{PIC_EINVAL, "particle buffer too small"};
+    });
+}
+
+pic_status pic_get_particle_cells(pic_ctx *ctx, int32_t *ci, int32_t *cj, double *fx, double *fy, int64_t cap,
+                                  int64_t *n_out)
+{
+    return guarded(ctx, [&] {
+        need_engine(ctx);
+        const int64_t n = ctx->eng->get_cells(ci, cj, fx, fy, cap);
         if (n_out) *n_out = n < 0 ? -n : n;
         if (n < 0) throw StatusError{PIC_EINVAL, "particle buffer too small"};
     });

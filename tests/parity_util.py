@@ -22,6 +22,11 @@ TOL = {"fp64": dict(field=1e-12, off=1e-12, mom=1e-12, band=1e-12),
 
 FIELD_COMPS = ["Er", "Eth", "Eph", "Br", "Bth", "Bph"]
 
+# own-norm gates apply to components at least this fraction of their vector
+# field's scale (below it FP32 resolves a component only to the rounding of
+# the vector, and the vector-scale gate holds it)
+OWN_MIN_RATIO = 1e-2
+
 
 def round_to_storage(P: dict, precision: str, nth: int) -> dict:
     """The particle state as the library stores it: int cell + in-cell
@@ -85,12 +90,18 @@ VECTORS = {"Er": ("Er", "Eth", "Eph"), "Eth": ("Er", "Eth", "Eph"), "Eph": ("Er"
            "Fr": ("Fr", "Fth", "Fph"), "Fth": ("Fr", "Fth", "Fph"), "Fph": ("Fr", "Fth", "Fph")}
 
 
-def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=None, vector_scale=False):
+def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=None, vector_scale=False,
+                   own_tol=None, floor=None):
     """Per-component inf-norm error relative to the component's own inf-norm;
     with vector_scale, relative to the largest inf-norm among the components
     of the same vector field (E, B or F) -- the scale FP32 rounding follows
     when one component is orders of magnitude below the others (the
-    Cartesian push mixes them)."""
+    Cartesian push mixes them) -- and, when own_tol is given, also relative
+    to the component's own inf-norm, gated at own_tol for components at
+    least OWN_MIN_RATIO of their vector's scale.  Both errors are
+    printed for every component.  floor (component -> absolute error) widens
+    the gate of a component to that absolute error where it is larger than
+    tol times the scale: the oracle's own rounding, see shifted_oracle."""
     worst = {}
     scale = {}
     if vector_scale:
@@ -99,19 +110,34 @@ def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=N
     for c in comps:
         a, b = s.get_field(c), o.get_field(c)
         assert a.shape == b.shape, (c, a.shape, b.shape)
+        own = rel_inf(a, b)
         if vector_scale:
             d = np.abs(a - b).max() if a.size else 0.0
             e = d / scale[c] if scale[c] > 0 else d
+            print(f"  {c}: {e:.2e} of its vector's scale, {own:.2e} of its own (|{c}| / |vector| "
+                  f"{np.abs(b).max() / scale[c] if scale[c] > 0 else 0.0:.1e})", flush=True)
         else:
-            e = rel_inf(a, b)
+            e = own
+        gate = tol
+        if floor is not None and c in floor:
+            sc = scale[c] if vector_scale else (np.abs(b).max() if b.size else 0.0)
+            fl = floor[c] / sc if sc > 0 else floor[c]
+            if fl > tol:
+                gate = fl
+                print(f"  {c}: {e:.2e}, gate widened from {tol:.1e} to the oracle's own rounding {fl:.2e}",
+                      flush=True)
         worst[c] = e
         if report is not None:
             report[c] = e
-        if e > tol:
+            if vector_scale:
+                report[c + "_own"] = own
+        if e > gate or (own_tol is not None and own > own_tol):  # printed; gated below
             k = np.unravel_index(np.abs(a - b).argmax(), a.shape)
             print(f"{c}: worst at row {k[0]} col {k[1]} gpu {a[k]:.9e} oracle {b[k]:.9e} max|oracle| "
                   f"{np.abs(b).max():.3e}", flush=True)
-        assert e <= tol, f"{c}: relative inf-norm error {e:.3e} > {tol:.1e}"
+        assert e <= gate, f"{c}: relative inf-norm error {e:.3e} > {gate:.1e}"
+        if own_tol is not None and (not vector_scale or np.abs(b).max() >= OWN_MIN_RATIO * scale[c]):
+            assert own <= own_tol, f"{c}: error {own:.3e} of its own inf-norm > {own_tol:.1e}"
     return worst
 
 
@@ -155,6 +181,15 @@ def compare_particles(o, s, tol, nth, band, report=None):
     return dict(off_x=ex, off_y=ey, mom=emom, in_band=in_band)
 
 
+def carry_atol(o, p: dict, prec: str):
+    """Per-node bound on the injection carry's difference after one step from
+    identical inputs: the carry grows by f_inj |sigma_j| dA_j / q_inj, sigma_j
+    from the stored E_r of row 0, whose error is bounded by the field
+    tolerance of E_r's inf-norm."""
+    er_scale = np.abs(o.get_field("Er")).max()
+    return TOL[prec]["field"] * er_scale * p["f_inj"] * o.geometry(4) / p["q_inj"] + 1e-12
+
+
 def random_fields(o, rng, scale=1e-3):
     """Random E and B obeying the conducting-wall and axis conditions."""
     out = {}
@@ -171,17 +206,60 @@ def random_fields(o, rng, scale=1e-3):
     return out
 
 
-def oracle_from_sim(s, params: dict) -> Oracle:
-    """A fresh oracle holding exactly the GPU context's state: E and B,
-    particles (FP32 offsets and momenta are exact in FP64), step index and
-    injection carry.  Stepping both once compares one step from identical
-    input bits (the face charges are outputs of the step, not inputs)."""
-    o = Oracle(params)
-    for comp in FIELD_COMPS:
-        o.set_field(comp, s.get_field(comp))
+def oracles_from_sim(s, params: dict, shifts=(False,)) -> list:
+    """Fresh oracles holding exactly the GPU context's state: E and B,
+    particles (cell indices and in-cell offsets as stored, momenta,
+    weights), step index and injection carry, read back once.  Stepping one
+    beside the context compares one step from identical input bits (the
+    face charges are outputs of the step, not inputs).  An oracle whose
+    entry of shifts is true has every absolute coordinate i + fx, j + fy it
+    forms moved up by one unit in its last place (y not in the last row of
+    cells, see shifted_floor)."""
+    fields = {comp: s.get_field(comp) for comp in FIELD_COMPS}
     P = s.particles()
-    if len(P["x"]):
-        o.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
-    o.set_step_index(s.counts()["step"])
-    o.set_carry(s.carry())
-    return o
+    # cell indices and offsets as stored: an FP64 context's offsets do not
+    # survive the absolute coordinate (x = i + fx rounds fx by ~1e-16 i),
+    # and the pole distance must be formed from the offset
+    X = s.particle_cells() if len(P["x"]) else None
+    step, carry = s.counts()["step"], s.carry()
+    out = []
+    for shift in shifts:
+        o = Oracle(params)
+        for comp, a in fields.items():
+            o.set_field(comp, a)
+        if X is not None:
+            fx, fy = X["fx"], X["fy"]
+            if shift:
+                a = X["ci"].astype(np.float64) + fx
+                fx = (a + np.spacing(a)) - X["ci"]
+                # not in the last row of cells: the oracle carries the
+                # distance to the pole exactly (y there is nth minus it), so
+                # a shift of y would move a particle by far more than the
+                # oracle's rounding relative to the pole
+                a = X["cj"].astype(np.float64) + fy
+                fy = np.where(X["cj"] < params["nth"] - 1, (a + np.spacing(a)) - X["cj"], fy)
+            o.add_particles_cells(X["ci"], fx, X["cj"], fy, P["ur"], P["ut"], P["up"], P["w"], P["id"])
+        o.set_step_index(step)
+        o.set_carry(carry)
+        out.append(o)
+    return out
+
+
+def oracle_from_sim(s, params: dict) -> Oracle:
+    """One oracle holding the GPU context's state (oracles_from_sim)."""
+    return oracles_from_sim(s, params)[0]
+
+
+def shifted_floor(o, o_shift, factor=4.0, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"]):
+    """The FP64 oracle's own rounding after one step, per component: it keeps
+    absolute grid coordinates, so each stored coordinate carries up to half
+    a unit in the last place of the axis length (1.1e-13 cells at 512), and
+    a move's displacement, the difference of two such coordinates, carries
+    the sum.  The face charges a nearly radial move deposits are
+    proportional to its tiny meridional displacement, so the oracle's
+    relative error there can reach 1e-11 while the library (cell index plus
+    offset) stays near 1e-16.  The response of the oracle's step to a shift
+    of every coordinate by one unit in the last place (o_shift, loaded with
+    shift=True, stepped beside o) measures that rounding; the gate of each
+    component is widened to factor times it."""
+    return {c: factor * np.abs(o_shift.get_field(c) - o.get_field(c)).max() for c in comps}

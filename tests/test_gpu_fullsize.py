@@ -4,28 +4,34 @@ the FP64 oracle running the same step on the host cores:
 
   * the dipole rotator, 1024 x 1024 cells, 64 particles per cell (67.1M),
     surface injection on: two steps (the first sorts, the second does not),
-    every field and every particle compared, FP64 and FP32 -- the FP32 case
-    one step at a time from identical input bits (the oracle reloaded from
-    the GPU state before each step), as the FP32 tolerance is per step;
-  * the plain FP64 method, 64 x 64 cells, 16 pairs per cell, 100 steps;
+    every field and every particle compared;
+  * the plain FP64 method, 64 x 64 cells, 16 pairs per cell, 100 steps, one
+    step compared at steps 1, 10 and 100;
   * the monopole rotator, 512 x 512, from an empty start: the first 30
-    steps of surface injection (FP32 checked one step at a time, at steps
-    10, 20 and 30);
+    steps of surface injection, one step compared at steps 10, 20 and 30;
   * the four smallest runs of the 64-run ensemble, stepped as one batch;
-  * the 2048 x 2048 precision-stress workload (201M particles): FP64 three
-    steps, FP32 two steps one at a time (particles compared after the last).
+  * the 2048 x 2048 precision-stress workload (201M particles): two steps
+    (particles compared after the last).
 
-The per-step tolerances are those of the small parity tests (parity_util),
-FP32 fields measured against the scale of their vector field (E, B or F:
-early in a rotator run the meridional and azimuthal parts are orders of
-magnitude below the radial one, and FP32 rounding follows the vector);
-over several steps they grow with the step count for FP64 (reordered
-floating-point atomics) and stay fixed for FP32.  For FP64 fields the
-oracle's own resolution sets the floor: it keeps absolute FP64 grid
-coordinates and forms the new ones from r' and cos(theta'), which carries a
-rounding of about eps * N / 2 cells per move on an N-cell axis; the face
-charges, and the fields they drive, inherit it.  The FP64 field tolerance is
-therefore 1e-12 * max(1, N / 256)."""
+Every compared step starts from identical input bits: before it the oracle
+is loaded with the GPU context's state (oracle_from_sim), so each step is
+held to the per-step tolerances of the small parity tests (parity_util),
+with no factor for the steps run before it.  FP32 fields are gated at 1e-5
+of the inf-norm of their vector field (E, B or F: FP32 rounding follows the
+vector, which the Cartesian push mixes) and at OWN_TOL_FP32 = 1e-4 of their
+own inf-norm where a component is at least 1e-2 of its vector's scale
+(early in the monopole rotator E_theta is 1.6e-2 of E_r, and its error
+against its own norm is then about 60 times the vector-scale one); both
+errors are printed for every component.  FP64 fields are gated at 1e-12 of
+their own inf-norm, widened where the oracle's own rounding is larger: the
+oracle keeps absolute grid coordinates (a unit in the last place is 1.1e-13
+cells at 512), and a nearly radial move deposits meridional face charge in
+proportion to its tiny meridional displacement, the difference of two such
+coordinates; a
+second oracle loaded with every coordinate shifted by one unit in the last
+place and stepped beside the first measures that rounding, and the gate is
+four times its response (parity_util.shifted_floor).  Multi-step runs are
+reported, not gated: floating-point atomics reorder sums."""
 import os
 import sys
 import time
@@ -34,7 +40,7 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import TOL, compare_fields, oracle_from_sim, round_to_storage
+from parity_util import TOL, carry_atol, compare_fields, oracle_from_sim, oracles_from_sim, shifted_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -105,23 +111,46 @@ def _compare_large(o, s, tol, nth, band):
     assert np.abs(Po["w"] - Ps["w"]).max() <= 1e-7 * np.abs(Po["w"]).max()
 
 
-def _field_tol(prec, p):
-    if prec == "fp32":
-        return TOL[prec]["field"]
-    return TOL[prec]["field"] * max(1.0, max(p["nr"], p["nth"]) / 256.0)
+# FP32: error against a component's own inf-norm (components at least 1e-2
+# of their vector's scale)
+OWN_TOL_FP32 = 1e-4
 
 
-def _pair(p, P, prec, capacity, ids=True):
-    from oracle.oracle import Oracle
+def _compare_step(o, s, p, prec, particles=True, o_shift=None):
+    """Fields (and particles) after one step from identical inputs; o_shift
+    (FP64) is the oracle stepped from coordinates shifted by one unit in
+    the last place."""
+    t = TOL[prec]
+    floor = shifted_floor(o, o_shift) if o_shift is not None else None
+    compare_fields(o, s, t["field"], vector_scale=prec == "fp32", own_tol=OWN_TOL_FP32 if prec == "fp32" else None,
+                   floor=floor)
+    if particles:
+        _compare_large(o, s, t, p["nth"], t["band"])
+
+
+def _step_from_gpu_state(s, p, prec, timed=True):
+    """The oracle loaded with the GPU state, then both stepped once; for an
+    FP64 context also the oracle loaded with shifted coordinates."""
+    o, *rest = oracles_from_sim(s, p, (False, True) if prec == "fp64" else (False,))
+    o_shift = rest[0] if rest else None
+    t0 = time.time()
+    s.step(1)
+    t1 = time.time()
+    o.step(1)
+    if timed:
+        _say(f"  gpu {t1 - t0:.2f} s, oracle {time.time() - t1:.1f} s, {o.n} particles, injected {o.counters()[0]}")
+    if o_shift is not None:
+        o_shift.step(1)
+    return o, o_shift
+
+
+def _sim(p, P, prec, capacity, ids=True):
+    """A context in the launch configuration of the benchmark holding P."""
     from paper_1407_1810_amd.binding import Sim
-    o = Oracle(p)
     s = Sim(p, precision=prec, capacity=capacity, tile=TILE, sort_interval=SORT_INTERVAL, chunk_ppt=PPT, ids=ids)
     if P is not None:
-        R = round_to_storage(P, prec, p["nth"])
-        o.add_particles(R["x"], R["y"], R["ur"], R["ut"], R["up"], R["w"], R["id"])
-        del R
         s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
-    return o, s
+    return s
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -132,98 +161,82 @@ def test_dipole_rotator_1024_full_size(prec):
     P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
     n = len(P["x"])
     _say(f"dipole rotator {prec}: {n} particles generated in {time.time() - t0:.1f} s")
-    o, s = _pair(p, P, prec, n + (4 << 20))
+    s = _sim(p, P, prec, n + (4 << 20))
     del P
-    t = TOL[prec]
+    inj = 0
     for k in range(2):
-        if prec == "fp32" and k > 0:
-            o = oracle_from_sim(s, p)
-        t0 = time.time()
-        s.step(1)
-        t1 = time.time()
-        o.step(1)
-        _say(f" step {k}: gpu {t1 - t0:.2f} s, oracle {time.time() - t1:.1f} s, injected {o.counters()[0]}")
-        sc = 1.0 if prec == "fp32" else (k + 1)
-        compare_fields(o, s, _field_tol(prec, p) * 2 * sc, vector_scale=prec == "fp32")
-        _compare_large(o, s, {kk: v * 2 * sc for kk, v in t.items()}, p["nth"], t["band"] * 2 * sc)
-    if prec == "fp64":
-        assert s.counts()["injected"] == o.counters()[0]
+        o, o_shift = _step_from_gpu_state(s, p, prec)
+        assert s.counts()["injected"] == o.counters()[0] + inj
+        inj = s.counts()["injected"]
+        _say(f" step {k} (sorts: {k == 0})")
+        _compare_step(o, s, p, prec, o_shift=o_shift)
+        del o, o_shift
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_precision_stress_2048_window(prec):
     """The 2048 x 2048 precision-stress workload (48 particles per cell,
     201M, injection on), whose long runs set the FP32 path beside the FP64
-    GPU path: both checked against the oracle over a short window, FP64 for
-    three steps run on, FP32 for two steps each from identical input bits."""
+    GPU path: both checked against the oracle over two steps, each from
+    identical input bits (particles compared after the second)."""
     cfg = W.config(3)
     p = cfg["params"]
     t0 = time.time()
     P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
     n = len(P["x"])
     _say(f"precision stress {prec}: {n} particles generated in {time.time() - t0:.1f} s")
-    o, s = _pair(p, P, prec, n + (8 << 20))
+    s = _sim(p, P, prec, n + (8 << 20))
     del P
-    t = TOL[prec]
-    steps = 3 if prec == "fp64" else 2
-    for k in range(steps):
-        if prec == "fp32" and k > 0:
-            o = oracle_from_sim(s, p)
-        t0 = time.time()
-        s.step(1)
-        t1 = time.time()
-        o.step(1)
-        _say(f" step {k}: gpu {t1 - t0:.2f} s, oracle {time.time() - t1:.1f} s, injected {o.counters()[0]}")
-        sc = 1.0 if prec == "fp32" else (k + 1)
-        compare_fields(o, s, _field_tol(prec, p) * 2 * sc, vector_scale=prec == "fp32")
-        if k == steps - 1:
-            _compare_large(o, s, {kk: v * 2 * sc for kk, v in t.items()}, p["nth"], t["band"] * 2 * sc)
-    if prec == "fp64":
-        assert s.counts()["injected"] == o.counters()[0]
+    inj = 0
+    for k in range(2):
+        o, o_shift = _step_from_gpu_state(s, p, prec)
+        assert s.counts()["injected"] == o.counters()[0] + inj
+        inj = s.counts()["injected"]
+        _say(f" step {k}")
+        _compare_step(o, s, p, prec, particles=k == 1, o_shift=o_shift)
+        del o, o_shift
 
 
 def test_plain_fp64_64x64_100_steps():
+    """The plain FP64 method over its 100 steps: one step from identical
+    input bits compared at steps 1, 10 and 100; the oracle run alongside
+    from the start is reported beside it (not gated)."""
     cfg = W.config(0)
     p = cfg["params"]
     P = W.pair_plasma(p, cfg["pairs_per_cell"], cfg["theta_T"], cfg["weight"], cfg["seed"])
-    o, s = _pair(p, P, "fp64", len(P["x"]) + (1 << 16))
-    t = TOL["fp64"]
+    s = _sim(p, P, "fp64", len(P["x"]) + (1 << 16))
+    o_run = oracle_from_sim(s, p)
     done = 0
-    for k in (1, 9, 90):
-        s.step(k)
-        o.step(k)
-        done += k
-        sc = 10.0 * done
-        _say(f"plain fp64 after {done} steps")
-        compare_fields(o, s, _field_tol("fp64", p) * sc)
-        _compare_large(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
+    for k in (1, 10, 100):
+        if k - done - 1 > 0:
+            s.step(k - done - 1)
+            o_run.step(k - done - 1)
+        o, o_shift = _step_from_gpu_state(s, p, "fp64", timed=False)
+        o_run.step(1)
+        done = k
+        _say(f"plain fp64, step {done}")
+        _compare_step(o, s, p, "fp64", o_shift=o_shift)
+        rep = {}
+        compare_fields(o_run, s, 1.0, report=rep)
+        _say(f"  run alongside from step 0 (reported): worst field {max(rep.values()):.2e}")
     assert done == cfg["steps"]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_monopole_rotator_512_first_steps(prec):
+    """The monopole rotator from its empty start: one step from identical
+    input bits compared at steps 10, 20 and 30 (injected pairs, their Philox
+    positions and the injection carry included)."""
     cfg = W.config(1)
     p = cfg["params"]
-    o, s = _pair(p, None, prec, 16 << 20)
-    t = TOL[prec]
+    s = _sim(p, None, prec, 16 << 20)
     for k in range(3):
-        if prec == "fp32":
-            # FP32: one step from identical input bits after the unchecked ones
-            s.step(9)
-            o = oracle_from_sim(s, p)
-            s.step(1)
-            o.step(1)
-        else:
-            s.step(10)
-            o.step(10)
-        sc = 2.0 if prec == "fp32" else 10.0 * (k + 1) * 10
+        s.step(9)
+        o, o_shift = _step_from_gpu_state(s, p, prec, timed=False)
         _say(f"monopole rotator {prec} after {10 * (k + 1)} steps: {o.n} particles")
-        compare_fields(o, s, _field_tol(prec, p) * sc, vector_scale=prec == "fp32")
-        _compare_large(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
+        _compare_step(o, s, p, prec, o_shift=o_shift)
+        assert np.all(np.abs(s.carry() - o.carry()) <= carry_atol(o, p, prec))
     assert o.n > 0
-    if prec == "fp64":
-        assert s.counts()["injected"] == o.counters()[0]
-    assert np.allclose(s.carry(), o.carry(), atol=1e-9 if prec == "fp64" else 1e-3)
 
 
 def test_smallest_ensemble_runs_as_one_batch():
@@ -235,16 +248,12 @@ def test_smallest_ensemble_runs_as_one_batch():
     for d in pick:
         p = d["params"]
         P = W.pair_plasma(p, d["pairs_per_cell"], d["theta_T"], d["weight"], d["seed"])
-        o, s = _pair(p, P, "fp32", 2 * len(P["x"]) + (1 << 20))
-        pairs.append((d, o, s))
+        pairs.append((d, None, _sim(p, P, "fp32", 2 * len(P["x"]) + (1 << 20))))
     b = Batch([s for _, _, s in pairs])
-    t = TOL["fp32"]
     for k in range(3):
-        if k > 0:
-            pairs = [(d, oracle_from_sim(s, d["params"]), s) for d, _, s in pairs]
+        pairs = [(d, oracle_from_sim(s, d["params"]), s) for d, _, s in pairs]
         b.step(1)
         for d, o, s in pairs:
             o.step(1)
             _say(f"{d['name']} step {k}")
-            compare_fields(o, s, _field_tol("fp32", d["params"]) * 5, vector_scale=True)
-            _compare_large(o, s, {kk: v * 5 for kk, v in t.items()}, d["params"]["nth"], t["band"] * 5)
+            _compare_step(o, s, d["params"], "fp32")

@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import (FIELD_COMPS, TOL, compare_fields, compare_particles, make_pair, random_fields,
-                         round_to_storage)
+from parity_util import (FIELD_COMPS, TOL, carry_atol, compare_fields, compare_particles, make_pair,
+                         oracle_from_sim, random_fields, round_to_storage)
 
 pytestmark = pytest.mark.gpu
 
@@ -105,16 +105,22 @@ def test_lds_and_global_paths_and_sort(prec):
     cfg, P = _small(nr=48, nth=40, pairs_per_cell=6, n_filt=2)
     p = cfg["params"]
     res = {}
+    t = TOL[prec]
     for si in (1, -1):
         o, s = make_pair(p, P, prec, sort_interval=si, tile=(4, 4))
-        o.step(3)
-        s.step(3)
-        t = dict(TOL[prec])
-        t = {k: v * 30 for k, v in t.items()}
-        compare_fields(o, s, t["field"])
-        compare_particles(o, s, t, p["nth"], t["band"])
+        for k in range(3):
+            if k > 0:
+                o = oracle_from_sim(s, p)
+            o.step(1)
+            s.step(1)
+            compare_fields(o, s, t["field"])
+            compare_particles(o, s, t, p["nth"], t["band"])
         res[si] = s.get_field("Er")
-    assert np.allclose(res[1], res[-1], rtol=0, atol=1e3 * TOL[prec]["field"] * np.abs(res[1]).max())
+    # the two paths after three steps, run on from the same start (reported
+    # scale: the reordered floating-point atomics of three steps)
+    d = np.abs(res[1] - res[-1]).max() / np.abs(res[1]).max()
+    _say(f"{prec}: sorted (LDS) and unsorted (global) paths differ by {d:.2e} after three steps")
+    assert d <= 1e3 * t["field"]
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
@@ -133,11 +139,12 @@ def test_capacity_equal_to_count_ragged_chunks(prec, ppt):
     o, s = make_pair(p, P, prec, capacity=n, chunk_ppt=ppt, tile=(4, 4), sort_interval=2)
     t = TOL[prec]
     for k in range(3):
+        if k > 0:
+            o = oracle_from_sim(s, p)
         o.step(1)
         s.step(1)
-        sc = 1.0 if k == 0 else 10.0 * (k + 1)
-        compare_fields(o, s, t["field"] * sc)
-        compare_particles(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
+        compare_fields(o, s, t["field"])
+        compare_particles(o, s, t, p["nth"], t["band"])
     assert s.counts()["live"] == o.n
 
 
@@ -266,16 +273,20 @@ def test_ten_steps_monopole_rotator_with_injection(prec):
     P = W.pair_plasma(p, 2, 0.2, cfg["weight"], 3)
     o, s = make_pair(p, P, prec, capacity=1 << 20)
     t = TOL[prec]
+    injected = 0
     for k in range(10):
+        if k > 0:
+            o = oracle_from_sim(s, p)
+        n0 = s.counts()["injected"]
         o.step(1)
         s.step(1)
         _say("rotator step", k, "n", o.n)
-        scale = 1.0 if prec == "fp32" else (k + 1)
-        compare_fields(o, s, t["field"] * 20 * scale)
-        compare_particles(o, s, {kk: v * 20 * scale for kk, v in t.items()}, p["nth"], t["band"] * 20 * scale)
-    assert o.counters()[0] > 0
-    assert s.counts()["injected"] == o.counters()[0]
-    assert np.allclose(s.carry(), o.carry(), atol=1e-9 if prec == "fp64" else 1e-4)
+        compare_fields(o, s, t["field"])
+        compare_particles(o, s, t, p["nth"], t["band"])
+        assert s.counts()["injected"] - n0 == o.counters()[0]
+        injected += o.counters()[0]
+        assert np.all(np.abs(s.carry() - o.carry()) <= carry_atol(o, p, prec))
+    assert injected > 0
 
 
 def test_edge_cases_poles_conductors_deletion():
@@ -294,14 +305,19 @@ def test_edge_cases_poles_conductors_deletion():
     P = dict(x=x, y=y, ur=ur, ut=ut, up=up, w=w, id=np.arange(len(x), dtype=np.uint64))
     for prec in PRECISIONS:
         o, s = make_pair(p, P, prec)
+        deleted = 0
         for k in range(6):
+            if k > 0:
+                o = oracle_from_sim(s, p)
+            d0 = s.counts()["deleted"]
             o.step(1)
             s.step(1)
             t = TOL[prec]
-            compare_fields(o, s, t["field"] * 10)
-            compare_particles(o, s, {kk: v * 10 for kk, v in t.items()}, p["nth"], t["band"] * 10)
-        assert o.counters()[1] >= 1  # something was deleted
-        assert s.counts()["deleted"] == o.counters()[1]
+            compare_fields(o, s, t["field"])
+            compare_particles(o, s, t, p["nth"], t["band"])
+            assert s.counts()["deleted"] - d0 == o.counters()[1]
+            deleted += o.counters()[1]
+        assert deleted >= 1  # something was deleted
 
 
 def test_error_codes():
