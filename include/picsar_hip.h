@@ -139,6 +139,21 @@ pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const 
                                 const double *ur, const double *ut, const double *up,
                                 const double *w, const uint64_t *id);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): the same append as
+ * pic_inject_particles, with the same arguments, results and errors, staged
+ * through a fixed block of device memory that the library holds on each GPU
+ * for the life of the process instead of memory allocated per call; it
+ * calls no allocating routine.  At most 65536 particles per call
+ * (PIC_EINVAL beyond).  Like pic_inject_particles it reads the particle
+ * count back and waits for the context's stream, so it cannot be recorded
+ * into a graph.  All contexts on one GPU share that block: calls that
+ * overlap on one GPU (from several host threads) race and must be
+ * serialised by the caller. */
+pic_status pic_inject_particles_noalloc(pic_ctx *ctx, int64_t n, const double *x, const double *y,
+                                        const double *ur, const double *ut, const double *up, const double *w,
+                                        const uint64_t *id);
+
 /* Advance n_steps steps: half Faraday, gather + push + deposit, half
  * Faraday, filter, Ampere with the conducting walls and the polar caps of
  * eq. (erpolarupdate), lossy layer, surface injection; particles are

@@ -31,7 +31,7 @@ AUTOTUNE_CANDIDATES = [(4, 8, 4), (4, 8, 8), (8, 8, 8), (4, 4, 4), (8, 16, 8), (
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_ECFL", -4: "PIC_ECAPACITY",
           -5: "PIC_ENAN", -6: "PIC_EDEVICE", -7: "PIC_ESTATE"}
 
-EXPORTED = ["pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape", "pic_get_field",
+EXPORTED = ["pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_inject_particles_noalloc", "pic_step", "pic_field_shape", "pic_get_field",
             "pic_set_field", "pic_get_particles", "pic_get_particle_cells", "pic_get_moments", "pic_set_step_index", "pic_set_carry",
             "pic_set_timing", "pic_set_sort", "pic_autotune", "pic_save", "pic_load", "pic_last_error", "pic_destroy",
             "pic_batch_create", "pic_batch_step", "pic_batch_elapsed_ms", "pic_batch_set_timing",
@@ -74,6 +74,7 @@ def lib():
         L.pic_init.argtypes = [vp, P(GridDesc), P(PhysDesc)]
         L.pic_init_grid.argtypes = [vp, P(GridDesc), P(PhysDesc)]
         L.pic_inject_particles.argtypes = [vp, i64] + [P(d)] * 6 + [P(u64)]
+        L.pic_inject_particles_noalloc.argtypes = [vp, i64] + [P(d)] * 6 + [P(u64)]
         L.pic_step.argtypes = [vp, i32]
         L.pic_field_shape.argtypes = [vp, i32, P(i32), P(i32), P(i32)]
         L.pic_get_field.argtypes = [vp, i32, P(d), i64]
@@ -99,7 +100,7 @@ def lib():
         L.pic_batch_last_error.argtypes = [vp]
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_destroy.argtypes = [vp]
-        for name in ("pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_step", "pic_field_shape",
+        for name in ("pic_create", "pic_init", "pic_init_grid", "pic_inject_particles", "pic_inject_particles_noalloc", "pic_step", "pic_field_shape",
                      "pic_get_field", "pic_set_field", "pic_get_particles", "pic_get_particle_cells",
                      "pic_get_moments",
                      "pic_set_step_index", "pic_set_carry", "pic_set_timing", "pic_set_sort", "pic_autotune",
@@ -205,6 +206,13 @@ class Sim:
         a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, ur, ut, up, w)]
         idp = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint64)
         self._check(lib().pic_inject_particles(self._h, len(a[0]), *[_dp(v) for v in a], _up(idp)))
+
+    def add_particles_noalloc(self, x, y, ur, ut, up, w, ids=None):
+        """add_particles through pic_inject_particles_noalloc (no device
+        allocation; at most 65536 particles per call)."""
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, ur, ut, up, w)]
+        idp = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint64)
+        self._check(lib().pic_inject_particles_noalloc(self._h, len(a[0]), *[_dp(v) for v in a], _up(idp)))
 
     def particles(self):
         n = int(self.counts()["live"])

@@ -28,7 +28,22 @@
 
 using namespace pic;
 
+// Device memory of the entry point that allocates nothing
+// (pic_inject_particles_noalloc): the staging of at most
+// kNoAllocMaxParticles particles -- six FP64 arrays and the uint64 ids -- on
+// their way to the particle store.  Every GPU the library runs on holds one
+// copy of it until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: its address on each device is
+// looked up once, with that device current (scratch_on, called by pic_init
+// and pic_load), and only that address is used.
+constexpr int64_t kNoAllocMaxParticles = 65536;
+static __device__ __align__(256) double scratch[7 * kNoAllocMaxParticles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
 
 struct HipError {
     hipError_t e;
@@ -61,6 +76,20 @@ void dev_fill(U *p, size_t n, U v, hipStream_t s)
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
     k_fill<U><<<std::max(blocks, 1), 256, 0, s>>>(p, n, v);
     HIPCHK(hipGetLastError());
+}
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// on the first call for the device and kept.
+double *scratch_on(int device)
+{
+    if (device < 0 || device >= kMaxDevices) throw StatusError{PIC_EINVAL, "device index beyond the supported range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[device] = static_cast<double *>(p);
+    }
+    return g_scratch[device];
 }
 
 // Per-stage device time from HIP events recorded between the launches of
@@ -418,6 +447,8 @@ public:
     virtual void init() = 0;
     virtual void inject(int64_t n, const double *x, const double *y, const double *ur, const double *ut,
                         const double *up, const double *w, const uint64_t *id) = 0;
+    virtual void inject_noalloc(int64_t n, const double *x, const double *y, const double *ur, const double *ut,
+                                const double *up, const double *w, const uint64_t *id, double *scratch) = 0;
     virtual void step(int n) = 0;
     virtual void get_field(int comp, double *out) = 0;
     virtual void set_field(int comp, const double *in) = 0;
@@ -677,6 +708,26 @@ public:
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipFree(stage));
         if (sid) HIPCHK(hipFree(sid));
+        inject_end(n, ntot);
+    }
+
+    // The same append staged through caller-free device memory: the seven
+    // arrays are copied straight from the caller's buffers into `scratch`
+    // (room for kNoAllocMaxParticles particles), then converted in place.
+    void inject_noalloc(int64_t n, const double *x, const double *y, const double *ur, const double *ut,
+                        const double *up, const double *w, const uint64_t *id, double *scratch) override
+    {
+        if (n == 0) return;
+        int cur = 0;
+        const unsigned long long ntot = inject_begin(n, x, y, w, cur);
+        const double *srcs[6] = {x, y, ur, ut, up, w};
+        for (int a = 0; a < 6; ++a)
+            HIPCHK(hipMemcpyAsync(scratch + (size_t)a * n, srcs[a], sizeof(double) * n, hipMemcpyHostToDevice,
+                                  stream));
+        uint64_t *sid = id ? reinterpret_cast<uint64_t *>(scratch + 6 * (size_t)n) : nullptr;
+        if (sid) HIPCHK(hipMemcpyAsync(sid, id, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream));
+        inject_load(scratch, sid, n, ntot, cur);
+        HIPCHK(hipStreamSynchronize(stream));
         inject_end(n, ntot);
     }
 
@@ -1518,6 +1569,7 @@ pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc
         e->ph = *phys;
         e->stream = ctx->stream;
         try {
+            scratch_on(ctx->device);
             e->init();
         } catch (...) {
             delete e;
@@ -1540,6 +1592,23 @@ pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const 
         if (n < 0 || (n > 0 && (!x || !y || !ur || !ut || !up || !w)))
             throw StatusError{PIC_EINVAL, "invalid particle arrays"};
         ctx->eng->inject(n, x, y, ur, ut, up, w, id);
+    });
+}
+
+pic_status pic_inject_particles_noalloc(pic_ctx *ctx, int64_t n, const double *x, const double *y,
+                                        const double *ur, const double *ut, const double *up, const double *w,
+                                        const uint64_t *id)
+{
+    return guarded(ctx, [&] {
+        need_engine(ctx);
+        if (n < 0 || (n > 0 && (!x || !y || !ur || !ut || !up || !w)))
+            throw StatusError{PIC_EINVAL, "invalid particle arrays"};
+        if (n > kNoAllocMaxParticles)
+            throw StatusError{PIC_EINVAL, "pic_inject_particles_noalloc takes at most " +
+                                              std::to_string(kNoAllocMaxParticles) + " particles per call"};
+        double *sp = g_scratch[ctx->device];
+        if (!sp) throw StatusError{PIC_ESTATE, "no staging memory on this device (pic_init has not run on it)"};
+        ctx->eng->inject_noalloc(n, x, y, ur, ut, up, w, id, sp);
     });
 }
 
@@ -1762,6 +1831,7 @@ pic_status pic_load(pic_ctx *ctx, const char *path)
             e->gd = h.grid;
             e->ph = h.phys;
             e->stream = ctx->stream;
+            scratch_on(ctx->device);
             e->init();
             e->restore(f, h);
         } catch (...) {
