@@ -10,14 +10,16 @@
 //
 //  k_step_begin ... particle-step count, sort decision, sort-span prefix
 //  k_sort_* ....... counting sort of particles by tile (serpentine order)
-//  k_open ......... close the sorts, lay out the push chunks, clear the
+//  k_open_faraday . close the sorts, lay out the push chunks, clear the
 //                   deposit planes (and, on a step without the sort
-//                   kernels, the bookkeeping of k_step_begin)
-//  k_faraday ...... half Faraday update of B (App. A, eq. (discreteeq))
+//                   kernels, the bookkeeping of k_step_begin); beside it
+//                   the first half Faraday update of B (App. A, eq.
+//                   (discreteeq))
 //  k_push ......... gather + Vay/Boris push + move + VB deposit, one
 //                   work-group per chunk of cell-sorted particles, fields and
 //                   face charges staged in LDS for the chunk's bounding box
-//  k_filter ....... the n_filt 1-2-1 passes with the polar remap (App. B),
+//  k_faraday_filter the second half Faraday update, and beside it the
+//                   n_filt 1-2-1 passes with the polar remap (App. B),
 //                   staged in LDS per tile
 //  k_ampere ....... Ampere update of E with the filtered face charges, polar
 //                   caps (eq. (erpolarupdate)), walls, lossy layer on E
@@ -80,14 +82,20 @@ enum : int {
 
 // Counting-sort key of a packed cell: tiles of tile_r x tile_th cells over
 // rows -G..nr+G, numbered in serpentine order so that consecutive tiles
-// share an edge; deleted particles get the last key.
+// share an edge; deleted particles get the last key.  The tile index
+// floor(x / d) of a row or column x (0 <= x < 2^21) is formed as
+// trunc((x + 1/2) * r) with r = 1/d rounded to FP32 on the host: (x + 1/2) / d
+// lies at least 1/(2d) from every integer, and the two roundings move it by
+// at most 2^-23 of itself, below 2^-2 / d, so the truncation is exact (and
+// much cheaper than an integer division by a value known only at run time).
 struct TileMap {
     int G, tile_r, tile_th, ntj, n_keys;
+    float inv_r, inv_th; // 1 / tile_r, 1 / tile_th rounded to FP32
     __device__ int key(uint32_t c) const
     {
         if (c == kDead) return n_keys;
-        const int ti = (cell_i(c) + G) / tile_r;
-        int tj = cell_j(c) / tile_th;
+        const int ti = (int)(((float)(cell_i(c) + G) + 0.5f) * inv_r);
+        int tj = (int)(((float)cell_j(c) + 0.5f) * inv_th);
         if (ti & 1) tj = ntj - 1 - tj;
         return ti * ntj + tj;
     }
@@ -278,21 +286,20 @@ __device__ void sort_finish_one(const RunDev<T> *__restrict__ runs, int n_runs, 
 // the layout of the push chunks), and every work-group clears its share of
 // the three deposit planes (256 threads x kZeroPerThread entries each).
 template <typename T>
-__global__ __launch_bounds__(256) void k_open(const RunDev<T> *__restrict__ runs, int n_runs,
-                                              const int *__restrict__ off, int begin, int span,
-                                              unsigned long long *__restrict__ span_off, int chunk,
-                                              unsigned long long *__restrict__ chunk_off,
-                                              unsigned int *__restrict__ work)
+__device__ inline void open_block(const RunDev<T> *__restrict__ runs, int n_runs, const int *__restrict__ off,
+                                  int begin, int span, unsigned long long *__restrict__ span_off, int chunk,
+                                  unsigned long long *__restrict__ chunk_off, unsigned int *__restrict__ work, int blk)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         if (begin) step_begin_one(runs, n_runs, span, span_off, 0);
         sort_finish_one(runs, n_runs, chunk, chunk_off, work);
     }
-    const int r = run_of(off, n_runs, blockIdx.x);
+    if (blk >= off[n_runs]) return; // padding
+    const int r = run_of(off, n_runs, blk);
     const RunDev<T> &R = runs[r];
     const size_t n = R.L.size();
     const gptr<T> f0 = glb(R.fld[cFR]), f1 = glb(R.fld[cFTH]), f2 = glb(R.fld[cFPH]);
-    const size_t b = (size_t)(blockIdx.x - off[r]) * (256 * kZeroPerThread) + threadIdx.x;
+    const size_t b = (size_t)(blk - off[r]) * (256 * kZeroPerThread) + threadIdx.x;
 #pragma unroll
     for (int q = 0; q < kZeroPerThread; ++q) {
         const size_t e = b + 256 * q;
@@ -352,17 +359,38 @@ __device__ __forceinline__ void faraday_rows(gptr<const T> __restrict__ Er, gptr
 // B_ph (i+1/2, j+1/2).  B_r is held at zero on the conductors and B_th on
 // the axis.
 template <typename T>
-__global__ __launch_bounds__(256) void k_faraday(const RunDev<T> *__restrict__ runs, int n_runs,
-                                                 const int *__restrict__ off, T hc_frac)
+__device__ inline void faraday_block(const RunDev<T> *__restrict__ runs, int n_runs, const int *__restrict__ off,
+                                     T hc_frac, int b, int tx, int ty)
 {
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int r = run_of(off, n_runs, b);
     const RunDev<T> &R = runs[r];
-    const Cell2 q = block_cell<kFieldRows>(b - off[r], R.L.nth + 1);
+    const Cell2 q = block_cell<kFieldRows>(b - off[r], R.L.nth + 1, tx, ty);
     if (q.j > R.L.nth) return;
     faraday_rows<T>(glb((const T *)R.fld[cER]), glb((const T *)R.fld[cETH]), glb((const T *)R.fld[cEPH]),
                     glb(R.fld[cBR]), glb(R.fld[cBTH]), glb(R.fld[cBPH]), R.m, R.L, q.i, q.j,
                     (double)hc_frac * R.cd);
+}
+
+// The step's opening launch: work-groups [0, nz_pad) close the sorts, lay
+// out the push chunks and clear the face-charge planes (nz_pad: the zeroing
+// map's work-groups padded to a multiple of eight, so that the XCD of a
+// work-group is its index modulo eight in both parts); the rest take the
+// first half Faraday update, which touches other arrays.
+template <typename T>
+__global__ __launch_bounds__(256) void k_open_faraday(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                      const int *__restrict__ off_zero, int nz_pad, int begin,
+                                                      int span, unsigned long long *__restrict__ span_off,
+                                                      int chunk, unsigned long long *__restrict__ chunk_off,
+                                                      unsigned int *__restrict__ work,
+                                                      const int *__restrict__ off_grid, int ng, T hc_frac)
+{
+    const int b = blockIdx.x;
+    if (b < nz_pad) {
+        open_block<T>(runs, n_runs, off_zero, begin, span, span_off, chunk, chunk_off, work, b);
+        return;
+    }
+    faraday_block<T>(runs, n_runs, off_grid, hc_frac, xcd_tile(b - nz_pad, ng), (int)threadIdx.x & 63,
+                     (int)threadIdx.x >> 6);
 }
 
 // E += (c circulation(B) - F) / area, then the lossy-layer factor on E;
@@ -494,20 +522,16 @@ __device__ inline T theta_pass(Ptr a, const Layout &L, int i, int j, int kind)
 constexpr int kFiltTR = 16, kFiltTC = 64;
 
 template <typename T, int H>
-__global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ runs, int n_runs,
-                                                const int *__restrict__ off)
+__device__ inline void filter_tile(const RunDev<T> *__restrict__ runs, int n_runs, const int *__restrict__ off,
+                                   int bt, int comp, T *sa, T *sb, T *st)
 {
     constexpr int NR = kFiltTR + 2 * H, NC = kFiltTC + 2 * H, N = NR * NC;
     constexpr int KN = (N + 255) / 256, KO = kFiltTR * kFiltTC / 256; // entries per thread: tile + halo, tile
     static_assert(kFiltTR * kFiltTC % 256 == 0, "the filter tile is a whole number of 256-entry sweeps");
-    static_assert(3 * N * sizeof(T) <= 65536, "the filter's LDS arrays fit in 64 KB");
-    __shared__ T sa[N], sb[N], st[N];
-    const int bt = xcd_tile(blockIdx.x, gridDim.x);
     const int r = run_of(off, n_runs, bt);
     const RunDev<T> &R = runs[r];
     const int passes = R.n_filt;
     const Layout L = R.L;
-    const int comp = blockIdx.y;
     const int kind = comp == 1 ? 1 : 0;
     const int nth = L.nth, ncol = kind ? nth : nth + 1;
     const int first = -L.G, last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
@@ -591,6 +615,36 @@ __global__ __launch_bounds__(256) void k_filter(const RunDev<T> *__restrict__ ru
         const int i = i0 + H + ci, j = j0 + H + cj;
         if (i <= last && j < ncol) dst[L.at(i, j)] = a[(H + ci) * NC + H + cj];
     }
+}
+
+// Filter tile sizes: kFiltTR x kFiltTC entries plus a halo of H.
+template <typename T, int H>
+struct FiltLds {
+    static constexpr int N = (kFiltTR + 2 * H) * (kFiltTC + 2 * H);
+    static_assert(3 * N * sizeof(T) <= 65536, "the filter's LDS arrays fit in 64 KB");
+};
+
+// The second half Faraday update and the filter of the face charges in one
+// launch (they touch disjoint arrays): work-groups [0, nf_pad) filter, one
+// (component, tile) each -- nf = 3 x the filter tiles of all runs, padded to
+// a multiple of eight so that the XCD of a work-group is its index modulo
+// eight in both parts -- and the rest update B, 64 x 4 threads each.
+template <typename T, int H>
+__global__ __launch_bounds__(256) void k_faraday_filter(const RunDev<T> *__restrict__ runs, int n_runs,
+                                                        const int *__restrict__ off_filt, int nf, int nf_pad,
+                                                        const int *__restrict__ off_grid, int ng, T hc_frac)
+{
+    __shared__ T sa[FiltLds<T, H>::N], sb[FiltLds<T, H>::N], st[FiltLds<T, H>::N];
+    const int b = blockIdx.x;
+    if (b < nf_pad) {
+        const int v = xcd_tile(b, nf_pad);
+        if (v >= nf) return; // the same for the whole work-group
+        const int per = nf / 3;
+        filter_tile<T, H>(runs, n_runs, off_filt, v % per, v / per, sa, sb, st);
+        return;
+    }
+    faraday_block<T>(runs, n_runs, off_grid, hc_frac, xcd_tile(b - nf_pad, ng), (int)threadIdx.x & 63,
+                     (int)threadIdx.x >> 6);
 }
 
 // The same pass on one integer-j array (the Gauss diagnostic's node charge).
@@ -1538,11 +1592,12 @@ constexpr int kSortSpan = 256 * 16;
 constexpr int kSortPer = kSortSpan / 256;
 
 // Tile keys a work-group counts in LDS: a window centred on the key of the
-// span's first particle.  Particles move a few cells between sorts, so the
-// keys of a span lie within a few tiles of each other (a few rows of tiles
-// in the serpentine order); a key outside the window goes to the global
-// counter directly.
-constexpr int kSortWin = 4096;
+// span's first live particle (of its first eight).  Particles move a few
+// cells between sorts, so the keys of a span lie within a few tiles of each
+// other (a few rows of tiles in the serpentine order, rows of up to a few
+// hundred tiles); a key outside the window goes to the global counter
+// directly.  The histogram and the scatter place the window alike.
+constexpr int kSortWin = 2048;
 
 // A key held by at most kSpanList spans of a sort is placed span by span in
 // span order, so that the sort is stable: every particle keeps the order of
@@ -1558,11 +1613,12 @@ constexpr int kSortWin = 4096;
 constexpr int kSpanList = 32;
 constexpr unsigned int kSpanOverflow = 1u << 20;
 
-__device__ __forceinline__ int sort_window_base(int first_key)
+__device__ __forceinline__ int sort_window_base(const TileMap &tm, gptr<const uint32_t> cs, uint32_t ns)
 {
-    return first_key > kSortWin / 2 ? first_key - kSortWin / 2 : 0;
+    int k0 = tm.key(cs[0]);
+    for (uint32_t q = 1; q < min(ns, 8u) && k0 == tm.n_keys; ++q) k0 = tm.key(cs[q]);
+    return k0 > kSortWin / 2 ? k0 - kSortWin / 2 : 0;
 }
-
 // Runs of equal keys among the 64 lanes of a wave (particles in lane
 // order, mostly of one tile after the previous sort): whether the lane
 // starts a run, the run's length (valid at its start) and the lane that
@@ -1629,7 +1685,7 @@ __global__ __launch_bounds__(256) void k_sort_hist(const RunDev<T> *__restrict__
             const uint32_t k = 256u * u + tid;
             cw[u] = k < ns ? cs[k] : kDead;
         }
-        const int base = sort_window_base(tm.key(cs[0]));
+        const int base = sort_window_base(tm, cs, ns);
         const gptr<unsigned int> nspan = glb(R.nspan);
         SpanEnt *const slist = R.slist; // struct copies need generic pointers
         const unsigned int sidx = (unsigned int)(gs - span_off[r]);
@@ -1726,20 +1782,22 @@ __global__ __launch_bounds__(256) void k_sort_spans(const RunDev<T> *__restrict_
     }
 }
 
-// Scatter into the other buffer.  Per span, in window of tile keys: each
-// particle's rank among the span's particles of its key in storage order --
-// the particles of the keys earlier in the span (a running count per key in
-// LDS), of the earlier waves for the same slice of 256 (a list of (key,
-// count) per wave), and of the earlier lanes of its own wave (a ballot per
-// distinct key) -- so that the ranks do not depend on the order in which
-// waves run.  Each key present then takes its block of slots: from the
-// key's span list (the key's particles in the spans before this one) when
-// the key is listed, else by a claim on the key's cursor; a key outside the
-// window is claimed by runs of equal keys in a wave, on its cursor.  The
-// particles are then copied, 4 per thread at a time, to offsets[key] +
-// block + rank.  Deleted particles (the last key) are dropped; lanes without
-// a particle write a spare slot past the capacity, so that every lane
-// stores.
+// Scatter into the other buffer, stably.  Wave w of the work-group takes
+// the quarter [1024 w, 1024 (w + 1)) of the span, 64 consecutive particles
+// per slice, so that a particle's rank among the span's particles of its
+// key in storage order is: the wave's particles of that key in its earlier
+// slices (a running count per wave and key in LDS, which only that wave
+// touches), the earlier lanes of its slice (a ballot per distinct key), and
+// the particles of the key in the earlier waves' quarters (their counts,
+// read after one barrier).  No rank depends on the order in which waves
+// run.  The first wave that met a key then takes the span's block of slots
+// for it: from the key's span list (the key's particles in the spans
+// before this one) when the key is listed, else by a claim on the key's
+// cursor; a key outside the window is claimed by runs of equal keys in a
+// wave, on its cursor.  The particles are copied, four slices per thread at
+// a time, to offsets[key] + block + rank.  Deleted particles (the last key)
+// are dropped; lanes without a particle write a spare slot past the
+// capacity, so that every lane stores.
 __device__ inline unsigned long long lanemask_lt(int lane)
 {
     return lane == 0 ? 0ull : ((1ull << lane) - 1ull);
@@ -1749,11 +1807,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restrict__ runs, int n_runs,
                                                       const unsigned long long *__restrict__ span_off)
 {
-    __shared__ unsigned int h[kSortWin];
-    __shared__ int2 wl[4][64]; // per wave: (key in the window, particles) of the current slice
-    __shared__ int nwl[4];
+    constexpr int Q = kSortSpan / 4;                // particles of a wave's quarter
+    __shared__ unsigned int h[kSortWin];            // per key of the window: the span's first slot
+    __shared__ unsigned short wc[4][kSortWin];      // per wave and key: the key's particles in its quarter
+    __shared__ unsigned short tl[4][Q];             // per wave: the keys it met, as window offsets
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
+    for (int e = tid; e < 4 * kSortWin; e += 256) (&wc[0][0])[e] = 0;
+    __syncthreads(); // the counts are clear; each span leaves them clear
     const unsigned long long nspan_all = span_off[n_runs];
     for (unsigned long long gs = blockIdx.x; gs < nspan_all; gs += gridDim.x) {
         const int r = __builtin_amdgcn_readfirstlane(run_of(span_off, n_runs, gs));
@@ -1772,18 +1833,21 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
         const SpanEnt *const slist = R.slist;
         const gptr<const unsigned int> sbefore = glb((const unsigned int *)R.sbefore);
         const uint32_t cap = (uint32_t)R.capacity;
+        const uint32_t q0 = (uint32_t)wv * Q + (uint32_t)lane;
         uint32_t cw[kSortPer];
 #pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
-            const uint32_t k = 256u * u + tid;
+            const uint32_t k = q0 + 64u * u;
             cw[u] = k < ns ? cs[k] : kDead;
         }
-        const int base = sort_window_base(tm.key(cs[0]));
-        __syncthreads(); // the window is clear
+        const int base = sort_window_base(tm, cs, ns);
+        // the wave's ranks: running counts of its keys, one ballot per
+        // distinct key of a slice
         uint32_t rank[kSortPer];
-#pragma unroll 1
+        int nt = 0; // keys the wave met (the same on every lane)
+#pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
-            const int key = 256u * u + tid < ns ? tm.key(cw[u]) : INT_MAX;
+            const int key = q0 + 64u * u < ns ? tm.key(cw[u]) : INT_MAX;
             const bool live = key != INT_MAX && key != tm.n_keys;
             const unsigned int dw = (unsigned int)(key - base);
             const bool inw = live && dw < (unsigned int)kSortWin;
@@ -1793,45 +1857,38 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
             if (kr.head && live && !inw)
                 got = (uint32_t)(offsets[key] + atomic_add_fetch_old(cursor + key, (unsigned int)kr.len));
             const uint32_t out_rank = (uint32_t)__shfl((int)got, kr.head_lane) + (uint32_t)(lane - kr.head_lane);
-            // inside: the lane's rank among the wave's lanes of its key, and
-            // the wave's (key, count) list, one entry per distinct key
             unsigned long long pending = __ballot(inw);
-            int nl = 0;
             uint32_t lrank = 0;
             while (pending) {
                 const int leader = __ffsll((long long)pending) - 1;
-                const int lk = __shfl(key, leader);
-                const unsigned long long m = __ballot(inw && key == lk);
-                if (inw && key == lk) lrank = (uint32_t)__popcll(m & lanemask_lt(lane));
-                if (lane == 0) wl[wv][nl] = make_int2(lk - base, __popcll(m));
-                ++nl;
+                const unsigned int ld = (unsigned int)(__shfl(key, leader) - base);
+                const unsigned long long m = __ballot(inw && dw == ld);
+                const unsigned int c = wc[wv][ld];
+                if (inw && dw == ld) lrank = c + (uint32_t)__popcll(m & lanemask_lt(lane));
+                if (lane == 0) {
+                    if (c == 0) tl[wv][nt] = (unsigned short)ld;
+                    wc[wv][ld] = (unsigned short)(c + (unsigned int)__popcll(m));
+                }
+                nt += c == 0;
                 pending &= ~m;
             }
-            if (lane == 0) nwl[wv] = nl;
-            __syncthreads();
-            uint32_t pre = 0;
-            if (inw) {
-                pre = h[dw];
-                for (int w2 = 0; w2 < wv; ++w2) {
-                    const int n2 = nwl[w2];
-                    for (int q = 0; q < n2; ++q) {
-                        const int2 e = wl[w2][q];
-                        if (e.x == (int)dw) pre += (uint32_t)e.y;
-                    }
-                }
-            }
-            rank[u] = inw ? pre + lrank : out_rank;
-            __syncthreads(); // every read of the running counts is done
-            if (lane < nl) {
-                const int2 e = wl[wv][lane];
-                atomicAdd(&h[e.x], (unsigned int)e.y);
-            }
+            rank[u] = inw ? lrank : out_rank;
         }
-        __syncthreads();
-        for (int e = tid; e < kSortWin; e += 256) {
-            const unsigned int v = h[e];
-            if (v) {
-                const int key = base + e;
+        __syncthreads(); // every wave's counts are complete
+        // the span's block of slots for each key, taken by the first wave
+        // (in wave order) that met it
+        for (int t = lane; t < nt; t += 64) {
+            const unsigned int ld = tl[wv][t];
+            bool first = true;
+            unsigned int v = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < 4; ++w2) {
+                const unsigned int c = wc[w2][ld];
+                first = first && !(w2 < wv && c != 0);
+                v += c;
+            }
+            if (first) {
+                const int key = base + (int)ld;
                 const unsigned int m = nspan[key];
                 unsigned long long blk = 0;
                 bool listed = false;
@@ -1844,25 +1901,33 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
                     }
                 }
                 if (!listed) blk = atomic_add_fetch_old(cursor + key, v);
-                h[e] = (unsigned int)(offsets[key] + blk);
+                h[ld] = (unsigned int)(offsets[key] + blk);
             }
         }
-        __syncthreads();
+        __syncthreads(); // every block of slots is known
         uint32_t dest[kSortPer];
 #pragma unroll
         for (int u = 0; u < kSortPer; ++u) {
             const int key = tm.key(cw[u]);
             const unsigned int dw = (unsigned int)(key - base);
-            uint32_t d = cap + (uint32_t)(tid & 63); // spare slot
-            if (256u * u + tid < ns && key != tm.n_keys) {
-                const uint32_t t = dw < (unsigned int)kSortWin ? h[dw] + rank[u] : rank[u];
+            uint32_t d = cap + (uint32_t)lane; // spare slot
+            if (q0 + 64u * u < ns && key != tm.n_keys) {
+                uint32_t t = rank[u];
+                if (dw < (unsigned int)kSortWin) {
+                    t += h[dw];
+                    for (int w2 = 0; w2 < wv; ++w2) t += wc[w2][dw];
+                }
                 if (t < cap) d = t;
                 else atomic_or(glb(R.status), 4); // never write outside the store
             }
             dest[u] = d;
         }
-        __syncthreads();
-        for (int e = tid; e < kSortWin; e += 256) h[e] = 0;
+        __syncthreads(); // every read of the counts and blocks is done
+        for (int t = lane; t < nt; t += 64) {
+            const unsigned int ld = tl[wv][t];
+            wc[wv][ld] = 0;
+            h[ld] = 0;
+        }
         gptr<const T> src[6];
         gptr<T> dst[6];
 #pragma unroll
@@ -1879,7 +1944,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const RunDev<T> *__restric
             uint64_t pid[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t k = 256u * (g + u) + tid;
+                const uint32_t k = q0 + 64u * (g + u);
                 const bool in = k < ns;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) pay[u][q] = in ? src[q][k] : (T)0;
@@ -1941,10 +2006,13 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ src, co
 // multiple of 2^-50 max|w| through the 1.5 * 2^52 shift (|v| <= max|w|, so
 // the integer stays below 2^51; a span adds at most 2^12 max|w| to an entry,
 // below 2^62) -- so that the sum of a span is exact and independent of the
-// order of the atomics, and each entry is flushed with one FP64 global
-// atomic; other spans add straight to global memory.  The grid covers the
-// store's capacity; work-groups past the particle count return at once.
-constexpr int kNodeSpan = 4096, kNodeLds = 4096;
+// order of the atomics.  Positive and negative particles go to two planes
+// (|Q| w each, four atomics per particle): rounding to the nearest integer
+// is odd-symmetric, so their difference is exactly the signed sum and their
+// sum the absolute one.  Each entry is flushed with one FP64 global atomic
+// per plane; other spans add straight to global memory.  The grid covers
+// the store's capacity; work-groups past the particle count return at once.
+constexpr int kNodeSpan = 4096, kNodeLds = 2048;
 
 __device__ __forceinline__ void lds_add_fixed(long long *a, double x)
 {
@@ -1952,16 +2020,26 @@ __device__ __forceinline__ void lds_add_fixed(long long *a, double x)
     atomicAdd((unsigned long long *)a, (unsigned long long)(__double_as_longlong(sh) - 0x4338000000000000ll));
 }
 
+// Both particle buffers of a context and its counters: the kernel reads
+// which buffer is current from the counters, so that the host need not.
 template <typename T>
-__global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict__ cell, const T *__restrict__ dx,
-                                                     const T *__restrict__ dy, const T *__restrict__ w,
-                                                     const unsigned long long *n_total, Layout L, double scale,
-                                                     double inv, double *__restrict__ rho,
-                                                     double *__restrict__ rabs)
+struct NodeSrc {
+    const uint32_t *cell[2];
+    const T *dx[2], *dy[2], *w[2];
+    const unsigned long long *ctr;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_node_charge(NodeSrc<T> src, Layout L, double scale, double inv,
+                                                     double *__restrict__ rho, double *__restrict__ rabs)
 {
     __shared__ long long acc[2][kNodeLds];
     __shared__ int red[4][4];
-    const unsigned long long n = *n_total;
+    const gptr<const unsigned long long> ctr = glb(src.ctr);
+    const unsigned long long n = ctr[kTotal];
+    const int cur = (int)ctr[kCur];
+    const gptr<const uint32_t> cell = glb(src.cell[cur]);
+    const gptr<const T> dx = glb(src.dx[cur]), dy = glb(src.dy[cur]), w = glb(src.w[cur]);
     const unsigned long long base = (unsigned long long)blockIdx.x * kNodeSpan;
     if (base >= n) return; // the same for the whole work-group
     const int cnt = (int)min((unsigned long long)kNodeSpan, n - base);
@@ -2001,28 +2079,39 @@ __global__ __launch_bounds__(256) void k_node_charge(const uint32_t *__restrict_
             acc[1][e] = 0;
         }
         __syncthreads();
-        for (int k = tid; k < cnt; k += 256) {
-            const uint32_t c = cell[base + k];
-            if (c == kDead) continue;
-            const int e = (cell_i(c) - imin) * nw + (cell_j(c) - jmin); // node (i, j); (i + 1, j) is e + nw
-            const double fx = dx[base + k], fy = dy[base + k], Q = w[base + k] * scale;
-            const double A = fabs(Q);
-            const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
-            lds_add_fixed(&acc[0][e], Q * w00);
-            lds_add_fixed(&acc[0][e + nw], Q * w10);
-            lds_add_fixed(&acc[0][e + 1], Q * w01);
-            lds_add_fixed(&acc[0][e + nw + 1], Q * w11);
-            lds_add_fixed(&acc[1][e], A * w00);
-            lds_add_fixed(&acc[1][e + nw], A * w10);
-            lds_add_fixed(&acc[1][e + 1], A * w01);
-            lds_add_fixed(&acc[1][e + nw + 1], A * w11);
+        // four particles per thread at a time, all their loads issued first
+        for (int k0 = tid; k0 < cnt; k0 += 4 * 256) {
+            uint32_t c[4];
+            double fx[4], fy[4], q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 256 * u;
+                const bool in = k < cnt;
+                c[u] = in ? cell[base + k] : kDead;
+                fx[u] = in ? (double)dx[base + k] : 0.0;
+                fy[u] = in ? (double)dy[base + k] : 0.0;
+                q[u] = in ? (double)w[base + k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (c[u] == kDead) continue;
+                const int e = (cell_i(c[u]) - imin) * nw + (cell_j(c[u]) - jmin); // (i + 1, j) is e + nw
+                long long *const a = acc[q[u] < 0.0 ? 1 : 0];
+                const double A = fabs(q[u]) * scale;
+                const double gx = fx[u], gy = fy[u];
+                lds_add_fixed(&a[e], A * ((1 - gx) * (1 - gy)));
+                lds_add_fixed(&a[e + nw], A * (gx * (1 - gy)));
+                lds_add_fixed(&a[e + 1], A * ((1 - gx) * gy));
+                lds_add_fixed(&a[e + nw + 1], A * (gx * gy));
+            }
         }
         __syncthreads();
         for (int e = tid; e < ne; e += 256) {
             const size_t g = L.at(imin + e / nw, jmin + e % nw);
-            const long long v = acc[0][e], a = acc[1][e];
-            if (v != 0) unsafeAtomicAdd(&rho[g], (double)v * inv);
-            if (a != 0) unsafeAtomicAdd(&rabs[g], (double)a * inv);
+            const long long p = acc[0][e], m = acc[1][e];
+            if (p != m) unsafeAtomicAdd(&rho[g], (double)(p - m) * inv);
+            if (p != 0 || m != 0)
+                unsafeAtomicAdd(&rabs[g], (double)((unsigned long long)p + (unsigned long long)m) * inv);
         }
     } else {
         for (int k = tid; k < cnt; k += 256) {

@@ -341,14 +341,19 @@ private:
             HIPCHK(hipGetLastError());
         }
         mark(t, s, kStSort, false);
+        // the opening launch: bookkeeping and the cleared deposit planes beside
+        // the first half Faraday update (timed as the Faraday stage; the
+        // zeroing stage stays empty)
         mark(t, s, kStZero, true);
-        k_open<T><<<tot_[kMapZero], 256, 0, s>>>(runs_, n_, map(kMapZero), sort ? 0 : 1, kSortSpan, span_off_,
-                                                 256 * ppt_, chunk_off_, work_);
-        HIPCHK(hipGetLastError());
         mark(t, s, kStZero, false);
         mark(t, s, kStFaraday, true);
-        k_faraday<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid), (T)0.5);
-        HIPCHK(hipGetLastError());
+        {
+            const int nz_pad = (tot_[kMapZero] + 7) / 8 * 8;
+            k_open_faraday<T><<<nz_pad + tot_[kMapGrid], 256, 0, s>>>(runs_, n_, map(kMapZero), nz_pad, sort ? 0 : 1,
+                                                                     kSortSpan, span_off_, 256 * ppt_, chunk_off_,
+                                                                     work_, map(kMapGrid), tot_[kMapGrid], (T)0.5);
+            HIPCHK(hipGetLastError());
+        }
         mark(t, s, kStFaraday, false);
         mark(t, s, kStPush, true);
         if (ppt_ == 4) k_push<T, 4><<<push_grid_, 256, shm_, s>>>(runs_, n_, chunk_off_, work_);
@@ -356,15 +361,24 @@ private:
         else k_push<T, 8><<<push_grid_, 256, shm_, s>>>(runs_, n_, chunk_off_, work_);
         HIPCHK(hipGetLastError());
         mark(t, s, kStPush, false);
-        k_faraday<T><<<tot_[kMapGrid], blk2, 0, s>>>(runs_, n_, map(kMapGrid), (T)0.5);
-        HIPCHK(hipGetLastError());
+        // the second half Faraday update beside the filter passes (timed as
+        // the filter stage)
         mark(t, s, kStFilter, true);
-        if (tot_[kMapFilter] > 0) {
-            const dim3 fg(tot_[kMapFilter], 3);
-            if (max_filt_ <= 2) k_filter<T, 2><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
-            else if (max_filt_ == 3) k_filter<T, 3><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
-            else if (max_filt_ <= 4) k_filter<T, 4><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
-            else k_filter<T, 8><<<fg, 256, 0, s>>>(runs_, n_, map(kMapFilter));
+        {
+            const int nf = 3 * tot_[kMapFilter], nf_pad = (nf + 7) / 8 * 8, ng = tot_[kMapGrid];
+            const int grid = nf_pad + ng;
+            if (max_filt_ <= 2)
+                k_faraday_filter<T, 2><<<grid, 256, 0, s>>>(runs_, n_, map(kMapFilter), nf, nf_pad, map(kMapGrid), ng,
+                                                             (T)0.5);
+            else if (max_filt_ == 3)
+                k_faraday_filter<T, 3><<<grid, 256, 0, s>>>(runs_, n_, map(kMapFilter), nf, nf_pad, map(kMapGrid), ng,
+                                                             (T)0.5);
+            else if (max_filt_ <= 4)
+                k_faraday_filter<T, 4><<<grid, 256, 0, s>>>(runs_, n_, map(kMapFilter), nf, nf_pad, map(kMapGrid), ng,
+                                                             (T)0.5);
+            else
+                k_faraday_filter<T, 8><<<grid, 256, 0, s>>>(runs_, n_, map(kMapFilter), nf, nf_pad, map(kMapGrid), ng,
+                                                             (T)0.5);
             HIPCHK(hipGetLastError());
         }
         mark(t, s, kStFilter, false);
@@ -865,18 +879,15 @@ public:
     // returns the plane that holds the filtered charge.
     const double *charge_planes()
     {
-        unsigned long long c[kNumCounters];
-        read_counters(c);
-        const int cur = (int)c[kCur];
         const size_t fsz = L.size();
         fill(grho_, fsz, 0.0);
         fill(gabs_, fsz, 0.0);
         const double qm = qmax_ > 0.0 ? qmax_ : 1.0;
         const int spans = (int)((cap_ + kNodeSpan - 1) / kNodeSpan);
-        k_node_charge<T><<<std::max(spans, 1), 256, 0, stream>>>(cell_[cur], arr_[cur][0], arr_[cur][1],
-                                                                arr_[cur][5], ctr_ + kTotal, L,
-                                                                std::ldexp(1.0, 50) / qm, qm * std::ldexp(1.0, -50),
-                                                                grho_, gabs_);
+        const NodeSrc<T> src{{cell_[0], cell_[1]}, {arr_[0][0], arr_[1][0]}, {arr_[0][1], arr_[1][1]},
+                             {arr_[0][5], arr_[1][5]}, ctr_};
+        k_node_charge<T><<<std::max(spans, 1), 256, 0, stream>>>(src, L, std::ldexp(1.0, 50) / qm,
+                                                                qm * std::ldexp(1.0, -50), grho_, gabs_);
         HIPCHK(hipGetLastError());
         double *a = grho_, *b = gtmp_;
         const dim3 blk(64, 4), fg((gd.nth + 1 + 63) / 64, (L.rows() + 3) / 4);
@@ -1152,7 +1163,7 @@ private:
         // sort tiles over rows -G..nr+G
         const int ntr = (L.rows() + tile_r - 1) / tile_r;
         const int ntj = (L.nth + tile_th - 1) / tile_th;
-        R.tm = TileMap{L.G, tile_r, tile_th, ntj, ntr * ntj};
+        R.tm = TileMap{L.G, tile_r, tile_th, ntj, ntr * ntj, 1.0f / (float)tile_r, 1.0f / (float)tile_th};
         R.sort_interval = sort_interval;
         counts_ = dalloc<unsigned int>(R.tm.n_keys + 1);
         cursor_ = dalloc<unsigned int>(R.tm.n_keys + 1);
