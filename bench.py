@@ -169,6 +169,32 @@ def run_gpu(cfg, P, precision, steps, warmup, tile, sort_interval, ppt, gauss=Tr
     return res
 
 
+def run_monopole(steps):
+    """The monopole rotator in FP64 from its empty start (512 x 512 cells,
+    surface injection only): `steps` steps replayed from the step graphs,
+    timed whole -- the particle count grows from zero, so the grid work
+    weighs in far more than on the preloaded workloads."""
+    from paper_1407_1810_amd import workloads as W
+    from paper_1407_1810_amd.binding import Sim
+    cfg = W.config(1)
+    p = cfg["params"]
+    s = Sim(p, precision="fp64", capacity=16 << 20, ids=False, tile=(4, 8), sort_interval=8)
+    c0 = s.counts()
+    sync_device()
+    t0 = time.perf_counter()
+    s.step(steps)
+    sync_device()
+    wall = time.perf_counter() - t0
+    c1 = s.counts()
+    s.close()
+    res = dict(workload=cfg["name"], precision="fp64", steps=steps,
+               value=(c1["particle_steps"] - c0["particle_steps"]) / wall, ms_per_step=1e3 * wall / steps,
+               particles_end=c1["live"], injected=c1["injected"])
+    log(f"[monopole fp64] {steps} steps from an empty start: {res['value']:.4e} particle-steps/s, "
+        f"{res['ms_per_step']:.3f} ms/step, {c1['live']} particles at the end")
+    return res
+
+
 def run_batched(n_runs, steps, warmup, tune_steps, seq):
     """The uneven ensemble in FP32: every run autotuned (sort tile and
     interval), then stepped together by one batch (one launch sequence per
@@ -337,8 +363,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=16)
     ap.add_argument("--stress-steps", type=int, default=16)
-    ap.add_argument("--parts", type=str, default="fp32,fp64,batched,stress,cpu",
-                    help="comma list of fp32, fp64, batched, stress (the 2048^2 workload in FP32), cpu")
+    ap.add_argument("--parts", type=str, default="fp32,fp64,batched,stress,mono,cpu",
+                    help="comma list of fp32, fp64, batched, stress (the 2048^2 workload in FP32), mono (the 512^2 "
+                         "monopole rotator in FP64 from its empty start), cpu")
+    ap.add_argument("--mono-steps", type=int, default=2000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -417,6 +445,7 @@ def main():
         rs["workload"] = c3["name"]
         rs["particles"] = 2 * c3["pairs_per_cell"] * c3["params"]["nr"] * c3["params"]["nth"]
         rs["cells"] = c3["params"]["nr"] * c3["params"]["nth"]
+    rm = run_monopole(args.mono_steps) if "mono" in parts else None
     out = {
         "metric": "particle-steps/sec (push+deposit+field), FP32 and batched vs FP64 GPU",
         "value": r32["value"] if r32 else None,
@@ -476,6 +505,8 @@ def main():
             "ms_per_step": rs["ms_per_step"], "steps": args.stress_steps, "sort_interval": rs["sort_interval"],
             "stage_ms": {k: round(v, 5) for k, v in rs["stage_ms"].items()},
             "roofline": roofline(bl, rs["stage_ms"]["push"], f"k_push<float,{args.ppt}>", copy_gbs, traffic)}
+    if rm:
+        out["monopole_fp64"] = rm
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 

@@ -244,9 +244,12 @@ public:
         HIPCHK(hipStreamSynchronize(s));
     }
 
-    void upload(const std::vector<RunDev<T>> &rd, hipStream_t s)
+    void upload(const std::vector<RunDev<T>> &rd, hipStream_t s) { upload(rd.data(), rd.size(), s); }
+    // (no host allocation: the append that allocates nothing passes its one
+    // run's entry directly)
+    void upload(const RunDev<T> *rd, size_t n, hipStream_t s)
     {
-        HIPCHK(hipMemcpyAsync(runs_, rd.data(), sizeof(RunDev<T>) * rd.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(runs_, rd, sizeof(RunDev<T>) * n, hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
     }
 
@@ -687,7 +690,7 @@ public:
         sched_need_ = true;
         gauss_unref();
         if (set_dep_scale()) {
-            plan_.upload({rd_}, stream);
+            plan_.upload(&rd_, 1, stream);
             ++version;
         }
     }
@@ -1125,7 +1128,7 @@ public:
         sched_need_ = c[kNeedSort] != 0;
         qmax_ = h.qmax;
         if (set_dep_scale()) {
-            plan_.upload({rd_}, stream);
+            plan_.upload(&rd_, 1, stream);
             ++version;
         }
     }

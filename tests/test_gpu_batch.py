@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import TOL, compare_fields, compare_particles, make_pair
+from parity_util import TOL, compare_fields, compare_particles, make_pair, oracle_from_sim
 
 pytestmark = pytest.mark.gpu
 
@@ -57,19 +57,23 @@ def test_batch_matches_the_oracle_run_by_run(prec):
         pairs.append((p, o, s))
     b = Batch([s for _, _, s in pairs])
     t = TOL[prec]
+    injected = [0] * len(pairs)
     for k in range(6):
         _say("batch", prec, "step", k)
+        # every step from identical input bits: each oracle reloaded from its run
+        if k:
+            pairs = [(p, oracle_from_sim(s, p), s) for p, _, s in pairs]
+        before = [s.particles() for _, _, s in pairs]
         b.step(1)
         for r, (p, o, s) in enumerate(pairs):
             o.step(1)
-            scale = 10.0 * (1.0 if prec == "fp32" else (k + 1))
-            compare_fields(o, s, t["field"] * scale)
-            compare_particles(o, s, {kk: v * scale for kk, v in t.items()}, p["nth"], t["band"] * scale)
+            compare_fields(o, s, t["field"])
+            compare_particles(o, s, t, p["nth"], t["band"], before=before[r])
             assert s.counts()["step"] == k + 1
+            injected[r] += o.counters()[0]
     inj = [s.counts()["injected"] for _, _, s in pairs]
     assert inj[0] > 0 and inj[2] > 0 and inj[1] == 0
-    for _, o, s in pairs:
-        assert s.counts()["injected"] == o.counters()[0]
+    assert inj == injected
     assert b.elapsed_ms() > 0.0
     b.close()
 
@@ -102,18 +106,21 @@ def test_batch_with_empty_runs_and_offset_steps(prec):
         runs.append((p, o, s, step0))
     b = Batch([s for _, _, s, _ in runs])
     t = TOL[prec]
+    injected = [0] * len(runs)
     for k in range(7):
+        if k:
+            runs = [(p, oracle_from_sim(s, p), s, step0) for p, _, s, step0 in runs]
+        before = [s.particles() for _, _, s, _ in runs]
         b.step(1)
-        for p, o, s, step0 in runs:
+        for r, (p, o, s, step0) in enumerate(runs):
             o.step(1)
-            scale = 10.0 * (1.0 if prec == "fp32" else (k + 1))
-            compare_fields(o, s, t["field"] * scale)
-            compare_particles(o, s, {kk: v * scale for kk, v in t.items()}, p["nth"], t["band"] * scale)
+            compare_fields(o, s, t["field"])
+            compare_particles(o, s, t, p["nth"], t["band"], before=before[r])
             assert s.counts()["step"] == step0 + k + 1
+            injected[r] += o.counters()[0]
     assert runs[1][2].counts()["injected"] > 0
     assert runs[2][2].counts()["live"] == 0
-    for _, o, s, _ in runs:
-        assert s.counts()["injected"] == o.counters()[0]
+    assert [s.counts()["injected"] for _, _, s, _ in runs] == injected
     b.close()
 
 
@@ -192,17 +199,22 @@ def test_autotune_and_resort_keep_parity(prec):
     n0 = s0.counts()["step"]
     _say("autotune", prec, best, ns, "steps", n0)
     assert n0 == (1 + 2) + (1 + 2) + (1 + 3)
+    # the oracle run alongside over the autotuning's steps: reported, and
+    # held only to a gross-error bound (its difference holds the reordered
+    # floating-point atomics of every step); the per-step bar follows
     o0.step(n0)
-    sc = 20.0 if prec == "fp32" else 10.0 * n0
-    compare_fields(o0, s0, t["field"] * sc)
-    compare_particles(o0, s0, {kk: v * sc for kk, v in t.items()}, p0["nth"], t["band"] * sc)
+    rep = {}
+    compare_fields(o0, s0, 1e-2, report=rep)
+    _say(f"  {prec} after autotuning, run alongside from step 0 (reported): worst field {max(rep.values()):.2e}")
+    # then every step from identical input bits, retiled and batched
     b = Batch([s0, s1])
-    b.step(2)
-    s1.set_sort(2, 16, 1)
-    b.step(2)
-    o0.step(4)
-    o1.step(4)
-    sc = 20.0 if prec == "fp32" else 10.0 * (n0 + 4)
-    for p, o, s in ((p0, o0, s0), (p1, o1, s1)):
-        compare_fields(o, s, t["field"] * sc)
-        compare_particles(o, s, {kk: v * sc for kk, v in t.items()}, p["nth"], t["band"] * sc)
+    for k in range(4):
+        if k == 2:
+            s1.set_sort(2, 16, 1)
+        o0, o1 = oracle_from_sim(s0, p0), oracle_from_sim(s1, p1)
+        before = [s0.particles(), s1.particles()]
+        b.step(1)
+        for r, (p, o, s) in enumerate(((p0, o0, s0), (p1, o1, s1))):
+            o.step(1)
+            compare_fields(o, s, t["field"])
+            compare_particles(o, s, t, p["nth"], t["band"], before=before[r])

@@ -1,7 +1,8 @@
 """The Michel monopole on the GPU (Sec. 5.4): the 512 x 512 monopole
 rotator (r_out = 12 r_in, R_l = 3 r_in, spin-up over 1/Omega, surface
-injection sized as in the benchmark workload) run in FP32 for two rotation
-periods (about 19,300 steps) through the library.  Checked inside the light
+injection sized as in the benchmark workload) run in FP32 and in FP64 (the
+workload's own precision) for two rotation periods (about 19,300 steps)
+through the library.  Checked inside the light
 cylinder, at 0.35, 0.5 and 0.7 R_l:
   * the winding B_phi / B_r = -r sin(theta) / R_l: the median over the
     latitudes away from the poles (the polar eighths excluded) of the ratio
@@ -31,14 +32,15 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def michel_gpu():
+@pytest.fixture(scope="module", params=["fp32", "fp64"])
+def michel_gpu(request):
     from paper_1407_1810_amd.binding import Sim, gpu_available
     if not gpu_available():
         pytest.skip("no HIP device")
     cfg = W.config(1)
     p = cfg["params"]
-    s = Sim(p, precision="fp32", capacity=160 << 20, ids=False, tile=(4, 8), sort_interval=8)
+    prec = request.param
+    s = Sim(p, precision=prec, capacity=64 << 20, ids=False, tile=(4, 8), sort_interval=8)
     Rl = p["c"] / p["omega"]
     nsteps = int(2.0 * 2.0 * math.pi / p["omega"])
     t0 = time.time()
@@ -47,11 +49,12 @@ def michel_gpu():
         k = min(2000, nsteps - done)
         s.step(k)
         done += k
-        _say(f"michel 512: step {done}/{nsteps}, {s.counts()['live']} particles, {time.time() - t0:.0f} s")
+        _say(f"michel 512 {prec}: step {done}/{nsteps}, {s.counts()['live']} particles, {time.time() - t0:.0f} s")
     fields = {c: s.get_field(c) for c in ("Er", "Eth", "Eph", "Br", "Bth", "Bph")}
     geo_rb = p["r_in"] * np.exp((np.arange(p["nr"]) + 0.5) * math.log(p["r_out"] / p["r_in"]) / p["nr"])
     geo_rn = p["r_in"] * np.exp(np.arange(p["nr"] + 1) * math.log(p["r_out"] / p["r_in"]) / p["nr"])
-    return p, Rl, fields, geo_rb, geo_rn
+    s.close()
+    return p, Rl, fields, geo_rb, geo_rn, prec
 
 
 def _sb(nth):
@@ -78,9 +81,9 @@ def _metrics(p, Rl, f, rb, rn, frac):
 
 @pytest.mark.parametrize("frac", [0.35, 0.5, 0.7])
 def test_michel_inside_the_light_cylinder(michel_gpu, frac):
-    p, Rl, f, rb, rn = michel_gpu
+    p, Rl, f, rb, rn, prec = michel_gpu
     lat, lum, e_over_b, eq = _metrics(p, Rl, f, rb, rn, frac)
-    _say(f"r = {frac} R_l: winding / Michel median {lat:.4f} (equator {eq:.4f}), L / L0 {lum:.4f}, "
+    _say(f"{prec}, r = {frac} R_l: winding / Michel median {lat:.4f} (equator {eq:.4f}), L / L0 {lum:.4f}, "
          f"E_theta / B_phi {e_over_b:.4f}")
     assert abs(lat - 1.0) < 0.08
     assert abs(lum - 1.0) < 0.08
