@@ -20,7 +20,7 @@
 //                   face charges staged in LDS for the chunk's bounding box
 //  k_faraday_filter the second half Faraday update, and beside it the
 //                   n_filt 1-2-1 passes with the polar remap (App. B),
-//                   staged in LDS per tile
+//                   by strips of 64 columns held in registers
 //  k_ampere ....... Ampere update of E with the filtered face charges, polar
 //                   caps (eq. (erpolarupdate)), walls, lossy layer on E
 //  k_close ........ surface pair injection (Sec. 5.3, eq. (volinjeq)), then
@@ -509,138 +509,119 @@ __device__ inline T theta_pass(Ptr a, const Layout &L, int i, int j, int kind)
     return v;
 }
 
-// All n_filt passes of the 1-2-1 filter over one face-charge plane of one
-// run in one launch (blockIdx.y = component).  A work-group stages a tile
-// of kFiltTR x kFiltTC entries with H rows and columns of halo (H >= the
-// run's passes), runs the passes in LDS -- each a theta half (the edge and
-// axis rules of the plane's parity) then a radial half, rows outside
-// [-G, last] and columns outside the plane held at zero -- and writes the
-// tile's centre to the second set of planes.  The valid part of the tile
-// shrinks by one row and column per pass, so H passes leave the centre
-// exact.  Each value is formed with the same operations, in the same
-// order, as one pass over the whole plane.
-constexpr int kFiltTR = 16, kFiltTC = 64;
+// All n_filt passes of the 1-2-1 filter over one face-charge plane, by
+// strips held in registers: a wave takes 64 consecutive columns, H of them
+// halo on each side, over kFiltRB rows plus H halo rows above and below
+// (H >= the run's passes).  Each pass forms the theta half (neighbouring
+// columns from the next lanes; the edge and axis rules of the plane's
+// parity: what spills across a pole folds back onto its mirror image, with
+// a plus sign for integer-j components and a minus sign for the theta
+// component) and then the radial half (the rows above and below in the
+// lane's own registers); entries outside the array, and those whose
+// neighbours lie outside the strip, are held at zero, so that the valid
+// part shrinks by one column and row per pass and H passes leave the
+// centre exact.  Each value is formed with the same operations, in the
+// same order, as one pass over the whole plane.  No LDS, no barriers.
+constexpr int kFiltRB = 32;
+template <int H>
+__host__ __device__ constexpr int filt_cols() { return 64 - 2 * H; } // useful columns of a strip
 
 template <typename T, int H>
-__device__ inline void filter_tile(const RunDev<T> *__restrict__ runs, int n_runs, const int *__restrict__ off,
-                                   int bt, int comp, T *sa, T *sb, T *st)
+__device__ inline void filter_strip(const RunDev<T> &R, int comp, int q, int lane)
 {
-    constexpr int NR = kFiltTR + 2 * H, NC = kFiltTC + 2 * H, N = NR * NC;
-    constexpr int KN = (N + 255) / 256, KO = kFiltTR * kFiltTC / 256; // entries per thread: tile + halo, tile
-    static_assert(kFiltTR * kFiltTC % 256 == 0, "the filter tile is a whole number of 256-entry sweeps");
-    const int r = run_of(off, n_runs, bt);
-    const RunDev<T> &R = runs[r];
-    const int passes = R.n_filt;
+    constexpr int U = filt_cols<H>(), NW = kFiltRB + 2 * H;
     const Layout L = R.L;
+    const int passes = R.n_filt;
     const int kind = comp == 1 ? 1 : 0;
     const int nth = L.nth, ncol = kind ? nth : nth + 1;
     const int first = -L.G, last = comp == 0 ? L.nr + L.G - 1 : L.nr + L.G;
-    const int lb = bt - off[r];
-    const int nbx = (nth + 1 + kFiltTC - 1) / kFiltTC;
-    const int by = lb / nbx, bx = lb - by * nbx;
-    const int i0 = first + by * kFiltTR - H, j0 = bx * kFiltTC - H; // entry (0, 0) of the tile
+    const int S = (nth + 1 + U - 1) / U;
+    const int sb = q % S, rb = q / S;
+    const int r0 = first + rb * kFiltRB; // first output row
+    if (r0 > last) return;
+    const int j = sb * U - H + lane;     // the lane's column
+    const bool jin = j >= 0 && j < ncol;
+    const int i0 = r0 - H;               // the strip's first row
     const gptr<const T> src = glb((const T *)R.fld[cFR + comp]);
     const gptr<T> dst = glb(R.ftmp[comp]);
-    const int tid = threadIdx.x;
-    // The entries of this thread, e = tid + 256 k, each with flags formed once:
-    // bit 0 the theta half is formed there (inside the array, off the tile's
-    // edge columns), bit 1 j > 0, bit 2 j + 1 < ncol, bits 3 and 4 the axis
-    // node j = 0 or nth mirrored onto j = 1 or nth - 1 (integer j), bits 5
-    // and 6 the odd parity at j = 0 or nth - 1 (half-integer j), bit 7 the
-    // radial half is formed there (inside the array, off the edge rows).
-    unsigned fl[KN];
-    {
-        // every load of the tile and its halo issued before the first LDS write
-        T v[KN];
+    // theta-half flags of the lane: bit 0 the half is formed (the column is in
+    // the array and both neighbours are in the strip), bit 1 j > 0, bit 2
+    // j + 1 < ncol, bits 3 and 4 the axis node j = 0 or nth mirrored onto
+    // j = 1 or nth - 1 (integer j), bits 5 and 6 the odd parity at j = 0 or
+    // nth - 1 (half-integer j)
+    const unsigned fl = (unsigned)(jin && lane >= 1 && lane <= 62) | (unsigned)(j > 0) << 1 |
+                        (unsigned)(j + 1 < ncol) << 2 | (unsigned)(kind == 0 && j == 1) << 3 |
+                        (unsigned)(kind == 0 && j == nth - 1) << 4 | (unsigned)(kind == 1 && j == 0) << 5 |
+                        (unsigned)(kind == 1 && j == nth - 1) << 6;
+    T v[NW];
 #pragma unroll
-        for (int k = 0; k < KN; ++k) {
-            const int e = tid + 256 * k;
-            const int li = e / NC, lj = e - li * NC;
-            const int i = i0 + li, j = j0 + lj;
-            const bool in = e < N && i >= first && i <= last && j >= 0 && j < ncol;
-            v[k] = in ? src[L.at(i, j)] : (T)0;
-            fl[k] = (unsigned)(in && lj >= 1 && lj < NC - 1) | (unsigned)(j > 0) << 1 | (unsigned)(j + 1 < ncol) << 2 |
-                    (unsigned)(kind == 0 && j == 1) << 3 | (unsigned)(kind == 0 && j == nth - 1) << 4 |
-                    (unsigned)(kind == 1 && j == 0) << 5 | (unsigned)(kind == 1 && j == nth - 1) << 6 |
-                    (unsigned)(in && li >= 1 && li < NR - 1) << 7;
-        }
-#pragma unroll
-        for (int k = 0; k < KN; ++k)
-            if (tid + 256 * k < N) sa[tid + 256 * k] = v[k];
+    for (int k = 0; k < NW; ++k) {
+        const int i = i0 + k;
+        v[k] = (jin && i >= first && i <= last) ? src[L.at(i, j)] : (T)0;
     }
-    T *a = sa, *b = sb;
     for (int p = 0; p < passes; ++p) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KN; ++k) { // theta half
-            const int e = tid + 256 * k;
-            if (e >= N) break;
-            const unsigned f = fl[k];
-            T v = (T)0;
-            if (f & 1u) {
-                const T *row = a + e; // row[0] is column j
-                const T r0 = row[0], rm = row[-1], rp = row[1];
-                v = (T)0.5 * r0;
-                v += (f & 2u) ? (T)0.25 * rm : (T)0;
-                v += (f & 4u) ? (T)0.25 * rp : (T)0;
-                v += (f & 8u) ? (T)0.25 * rm : (T)0;  // the axis node j = 0, mirrored
-                v += (f & 16u) ? (T)0.25 * rp : (T)0; // the axis node j = nth, mirrored
-                v -= (f & 32u) ? (T)0.25 * r0 : (T)0; // odd parity across the axis
-                v -= (f & 64u) ? (T)0.25 * r0 : (T)0;
+        // the theta half of row k, formed where the row is in the array
+        auto theta = [&](int k) -> T {
+            const T r0v = v[k];
+            const T rm = __shfl_up(r0v, 1), rp = __shfl_down(r0v, 1);
+            const int i = i0 + k;
+            T t = (T)0;
+            if ((fl & 1u) && i >= first && i <= last) {
+                t = (T)0.5 * r0v;
+                t += (fl & 2u) ? (T)0.25 * rm : (T)0;
+                t += (fl & 4u) ? (T)0.25 * rp : (T)0;
+                t += (fl & 8u) ? (T)0.25 * rm : (T)0;  // the axis node j = 0, mirrored
+                t += (fl & 16u) ? (T)0.25 * rp : (T)0; // the axis node j = nth, mirrored
+                t -= (fl & 32u) ? (T)0.25 * r0v : (T)0; // odd parity across the axis
+                t -= (fl & 64u) ? (T)0.25 * r0v : (T)0;
             }
-            st[e] = v;
-        }
-        __syncthreads();
+            return t;
+        };
+        // the radial half of row k from the theta halves of rows k - 1, k, k + 1
+        T tm = (T)0, t0 = theta(0);
 #pragma unroll
-        for (int k = 0; k < KN; ++k) { // radial half
-            const int e = tid + 256 * k;
-            if (e >= N) break;
-            T v = (T)0;
-            if (fl[k] & 128u) {
-                v = (T)0.5 * st[e];
-                v += (T)0.25 * st[e - NC];
-                v += (T)0.25 * st[e + NC];
+        for (int k = 0; k < NW; ++k) {
+            const T t1 = k + 1 < NW ? theta(k + 1) : (T)0;
+            const int i = i0 + k;
+            T w = (T)0;
+            if (jin && i >= first && i <= last && k >= 1 && k <= NW - 2) {
+                w = (T)0.5 * t0;
+                w += (T)0.25 * tm;
+                w += (T)0.25 * t1;
             }
-            b[e] = v;
+            v[k] = w;
+            tm = t0;
+            t0 = t1;
         }
-        T *t = a;
-        a = b;
-        b = t;
     }
-    __syncthreads();
+    if (lane >= H && lane < 64 - H && jin) {
 #pragma unroll
-    for (int k = 0; k < KO; ++k) {
-        const int e = tid + 256 * k;
-        const int ci = e / kFiltTC, cj = e - ci * kFiltTC;
-        const int i = i0 + H + ci, j = j0 + H + cj;
-        if (i <= last && j < ncol) dst[L.at(i, j)] = a[(H + ci) * NC + H + cj];
+        for (int k = H; k < H + kFiltRB; ++k) {
+            const int i = i0 + k;
+            if (i <= last) dst[L.at(i, j)] = v[k];
+        }
     }
 }
 
-// Filter tile sizes: kFiltTR x kFiltTC entries plus a halo of H.
-template <typename T, int H>
-struct FiltLds {
-    static constexpr int N = (kFiltTR + 2 * H) * (kFiltTC + 2 * H);
-    static_assert(3 * N * sizeof(T) <= 65536, "the filter's LDS arrays fit in 64 KB");
-};
-
 // The second half Faraday update and the filter of the face charges in one
-// launch (they touch disjoint arrays): work-groups [0, nf_pad) filter, one
-// (component, tile) each -- nf = 3 x the filter tiles of all runs, padded to
-// a multiple of eight so that the XCD of a work-group is its index modulo
-// eight in both parts -- and the rest update B, 64 x 4 threads each.
+// launch (they touch disjoint arrays): work-groups [0, nf_pad) filter, four
+// waves each, one strip (filter_strip) per wave -- nf = 3 x the filter
+// work-groups of all runs, padded to a multiple of eight so that the XCD of
+// a work-group is its index modulo eight in both parts -- and the rest
+// update B, 64 x 4 threads each.
 template <typename T, int H>
 __global__ __launch_bounds__(256) void k_faraday_filter(const RunDev<T> *__restrict__ runs, int n_runs,
                                                         const int *__restrict__ off_filt, int nf, int nf_pad,
                                                         const int *__restrict__ off_grid, int ng, T hc_frac)
 {
-    __shared__ T sa[FiltLds<T, H>::N], sb[FiltLds<T, H>::N], st[FiltLds<T, H>::N];
     const int b = blockIdx.x;
     if (b < nf_pad) {
         const int v = xcd_tile(b, nf_pad);
         if (v >= nf) return; // the same for the whole work-group
-        const int per = nf / 3;
-        filter_tile<T, H>(runs, n_runs, off_filt, v % per, v / per, sa, sb, st);
+        const int per = nf / 3, comp = v / per, lb = v - comp * per;
+        const int r = run_of(off_filt, n_runs, lb);
+        const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+        filter_strip<T, H>(runs[r], comp, 4 * (lb - off_filt[r]) + wv, lane);
         return;
     }
     faraday_block<T>(runs, n_runs, off_grid, hc_frac, xcd_tile(b - nf_pad, ng), (int)threadIdx.x & 63,

@@ -204,12 +204,17 @@ public:
         for (int m = 0; m < kMaps; ++m) tot_[m] = 0;
         max_filt_ = 0;
         any_sort_ = false;
+        for (int r = 0; r < n_; ++r) max_filt_ = std::max(max_filt_, rd[r].n_filt);
+        // filter strips: 64 columns less a halo of H on each side, H the
+        // filter kernel's build for the largest pass count
+        const int fH = max_filt_ <= 2 ? 2 : (max_filt_ == 3 ? 3 : (max_filt_ <= 4 ? 4 : 8));
+        const int fU = 64 - 2 * fH;
         for (int r = 0; r < n_; ++r) {
             const RunDev<T> &R = rd[r];
             const int nbx = (R.L.nth + 1 + 63) / 64;
             const int cnt[kMaps] = {
                 nbx * ((R.L.nr + 1 + 4 * kFieldRows - 1) / (4 * kFieldRows)),
-                R.n_filt > 0 ? ((R.L.nth + 1 + kFiltTC - 1) / kFiltTC) * ((R.L.rows() + kFiltTR - 1) / kFiltTR) : 0,
+                R.n_filt > 0 ? ((R.L.nth + 1 + fU - 1) / fU * ((R.L.rows() + kFiltRB - 1) / kFiltRB) + 3) / 4 : 0,
                 R.absorb_cells > 0 ? nbx * ((R.absorb_cells + 2 + 4 * kFieldRows - 1) / (4 * kFieldRows)) : 0,
                 (int)((R.L.size() + 256 * kZeroPerThread - 1) / (256 * kZeroPerThread)),
                 R.sort_interval > 0 ? (R.tm.n_keys + 1 + 255) / 256 : 0,
@@ -218,7 +223,6 @@ public:
                 h[(size_t)m * (n_ + 1) + r] = tot_[m];
                 tot_[m] += cnt[m];
             }
-            max_filt_ = std::max(max_filt_, R.n_filt);
             any_sort_ = any_sort_ || R.sort_interval > 0;
             max_cap = std::max(max_cap, R.lds_cap);
             cap_sum += std::max<long long>(R.capacity, 1);
