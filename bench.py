@@ -195,7 +195,7 @@ def run_monopole(steps):
     return res
 
 
-def run_batched(n_runs, steps, warmup, tune_steps, seq):
+def run_batched(n_runs, steps, warmup, tune_steps, seq, ppt=16):
     """The uneven ensemble in FP32: every run autotuned (sort tile and
     interval), then stepped together by one batch (one launch sequence per
     step, replayed from a HIP graph) and, for comparison, one run after the
@@ -215,7 +215,7 @@ def run_batched(n_runs, steps, warmup, tune_steps, seq):
         n0 += n
         # room for the surface injection of the tuning, warm-up and timed steps
         # (sized to stay near half the preload over that window)
-        s = Sim(p, precision="fp32", capacity=2 * n + (4 << 20), ids=False)
+        s = Sim(p, precision="fp32", capacity=2 * n + (4 << 20), ids=False, chunk_ppt=ppt)
         s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"])
         del P
         best, _ = s.autotune(steps=tune_steps)
@@ -377,6 +377,7 @@ def main():
                          "timed window holds whole sort intervals")
     ap.add_argument("--ppt", type=int, default=16, help="particles per thread of a push work-group (4, 8, 16)")
     ap.add_argument("--batched-runs", type=int, default=64)
+    ap.add_argument("--batched-ppt", type=int, default=16, help="particles per thread of the batch's push")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-warmup", type=int, default=50)
     ap.add_argument("--batched-tune-steps", type=int, default=4)
@@ -400,7 +401,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is not sharded across "
-              f"GPUs in this build", file=sys.stderr)
+              f"GPUs", file=sys.stderr)
         sys.exit(2)
     parts = set(args.parts.split(","))
     for flag, part in ((args.no_fp64, "fp64"), (args.no_cpu_baseline, "cpu"), (args.no_batched, "batched"),
@@ -432,7 +433,8 @@ def main():
     cpu = cpu_baseline(cfg, P) if "cpu" in parts else None
     del P
     if "batched" in parts:
-        rb = run_batched(args.batched_runs, args.batched_steps, args.batched_warmup, args.batched_tune_steps, True)
+        rb = run_batched(args.batched_runs, args.batched_steps, args.batched_warmup, args.batched_tune_steps, True,
+                         args.batched_ppt)
     if "stress" in parts:
         c3 = W.config(3)
         t0 = time.perf_counter()

@@ -120,11 +120,11 @@ pic_status pic_create(pic_ctx **out, int device, void *hip_stream);
  * diagnostic planes and the metric tables: the stretched coordinates of
  * Sec. 3.2 (xi = r0 ln(r / r0), theta_A = -cos theta, or their linear
  * options) and the area and line elements of App. A eq. (linearea), formed
- * in FP64 on the host and stored in the context's precision.  Once per
- * context; PIC_ESTATE if called twice, PIC_EINVAL for an invalid
- * descriptor, PIC_ENOMEM if the device memory runs out (nothing is then
- * kept).  pic_init_grid is the same call under the name of the scope
- * table's boundary. */
+ * in FP64 on the host and kept in FP64 on the device for the field update
+ * in either precision (the push reads the radii in the context's
+ * precision).  Once per context; PIC_ESTATE if called twice, PIC_EINVAL for
+ * an invalid descriptor, PIC_ENOMEM if the device memory runs out (nothing
+ * is then kept).  pic_init_grid is the same call under a second name. */
 pic_status pic_init(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys);
 pic_status pic_init_grid(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys_desc *phys);
 
