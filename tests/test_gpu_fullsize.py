@@ -10,6 +10,8 @@ the FP64 oracle running the same step on the host cores:
   * the monopole rotator, 512 x 512, from an empty start: the first 30
     steps of surface injection, one step compared at steps 10, 20 and 30;
   * the four smallest runs of the 64-run ensemble, stepped as one batch;
+  * the whole ensemble (64 runs, 320M particles), each run autotuned as the
+    benchmark does, then one batched step of every run compared;
   * the 2048 x 2048 precision-stress workload (201M particles): two steps
     (particles compared after the last).
 
@@ -30,8 +32,11 @@ proportion to its tiny meridional displacement, the difference of two such
 coordinates; a
 second oracle loaded with every coordinate shifted by one unit in the last
 place and stepped beside the first measures that rounding, and the gate is
-four times its response (parity_util.shifted_floor).  Multi-step runs are
-reported, not gated: floating-point atomics reorder sums."""
+four times its response (parity_util.shifted_floor).  Momenta are gated
+against the largest of the particle's old and new momentum and the largest
+term of its update (plus 1e-3).
+Multi-step runs are reported, not gated: floating-point atomics reorder
+sums."""
 import os
 import sys
 import time
@@ -40,7 +45,8 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import TOL, carry_atol, compare_fields, oracle_from_sim, oracles_from_sim, shifted_floor
+from parity_util import (TOL, carry_atol, compare_fields, momentum_scale, oracle_from_sim, oracles_from_sim,
+                         shifted_floor, widen_by_update_terms)
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +91,14 @@ def _by_id(P):
     return out, n0
 
 
-def _compare_large(o, s, tol, nth, band):
+def _compare_large(o, s, tol, nth, band, before=None):
+    """Particles matched by id; the momentum error is taken against |u| +
+    1e-3 with |u| the larger of the oracle's new momentum and, when the
+    state before the step is given, the old one and the update's largest
+    field term (parity_util.momentum_scale and widen_by_update_terms: a
+    particle a strong field stops within the step keeps the rounding of the
+    momentum it had, and one at rest in a nearly cancelling field the
+    rounding of the field's terms)."""
     Po, no = _by_id(o.particles())
     Ps, ns = _by_id(s.particles())
     assert no == ns and len(Po["x"]) == len(Ps["x"]), (no, ns, len(Po["x"]), len(Ps["x"]))
@@ -102,10 +115,22 @@ def _compare_large(o, s, tol, nth, band):
     same = (io == ig) & (jo == jg)
     ex = np.abs(Po["x"] - Ps["x"])[same].max(initial=0.0)
     ey = np.abs(Po["y"] - Ps["y"])[same].max(initial=0.0)
-    umag = np.sqrt(Po["ur"] ** 2 + Po["ut"] ** 2 + Po["up"] ** 2)
+    unew = np.sqrt(Po["ur"] ** 2 + Po["ut"] ** 2 + Po["up"] ** 2)
+    umag = unew if before is None else np.maximum(unew, momentum_scale(before, Po["id"]))
     du = np.sqrt((Po["ur"] - Ps["ur"]) ** 2 + (Po["ut"] - Ps["ut"]) ** 2 + (Po["up"] - Ps["up"]) ** 2)
-    emom = (du / (umag + 1e-3)).max(initial=0.0)
-    _say(f"  particles {len(Po['x'])}: offsets {ex:.2e} {ey:.2e}, momenta {emom:.2e}, in-band cells {in_band}")
+    raised = 0
+    if before is not None:
+        umag, raised = widen_by_update_terms(o, before, Po["id"], umag, du, tol["mom"])
+    rel = du / (umag + 1e-3)
+    emom = rel.max(initial=0.0)
+    _say(f"  particles {len(Po['x'])}: offsets {ex:.2e} {ey:.2e}, momenta {emom:.2e} (against the new momentum "
+         f"alone {(du / (unew + 1e-3)).max(initial=0.0):.2e}; {raised} scaled by the update's field terms), "
+         f"in-band cells {in_band}")
+    if emom > tol["mom"]:
+        for q in np.argsort(rel)[-4:]:
+            _say(f"  worst particle id {int(Po['id'][q])}: oracle u ({Po['ur'][q]:.6e}, {Po['ut'][q]:.6e}, "
+                 f"{Po['up'][q]:.6e}), gpu u ({Ps['ur'][q]:.6e}, {Ps['ut'][q]:.6e}, {Ps['up'][q]:.6e}), "
+                 f"momentum scale {umag[q]:.3e}")
     assert ex <= tol["off"] and ey <= tol["off"]
     assert emom <= tol["mom"]
     assert np.abs(Po["w"] - Ps["w"]).max() <= 1e-7 * np.abs(Po["w"]).max()
@@ -116,23 +141,25 @@ def _compare_large(o, s, tol, nth, band):
 OWN_TOL_FP32 = 1e-4
 
 
-def _compare_step(o, s, p, prec, particles=True, o_shift=None):
+def _compare_step(o, s, p, prec, particles=True, o_shift=None, before=None):
     """Fields (and particles) after one step from identical inputs; o_shift
     (FP64) is the oracle stepped from coordinates shifted by one unit in
-    the last place."""
+    the last place, before the particles at the start of the step."""
     t = TOL[prec]
     floor = shifted_floor(o, o_shift) if o_shift is not None else None
     compare_fields(o, s, t["field"], vector_scale=prec == "fp32", own_tol=OWN_TOL_FP32 if prec == "fp32" else None,
                    floor=floor)
     if particles:
-        _compare_large(o, s, t, p["nth"], t["band"])
+        _compare_large(o, s, t, p["nth"], t["band"], before)
 
 
 def _step_from_gpu_state(s, p, prec, timed=True):
     """The oracle loaded with the GPU state, then both stepped once; for an
-    FP64 context also the oracle loaded with shifted coordinates."""
+    FP64 context also the oracle loaded with shifted coordinates.  Returns
+    the oracle, the shifted one and the momenta at the start of the step."""
     o, *rest = oracles_from_sim(s, p, (False, True) if prec == "fp64" else (False,))
     o_shift = rest[0] if rest else None
+    before = _momenta(o)
     t0 = time.time()
     s.step(1)
     t1 = time.time()
@@ -141,7 +168,13 @@ def _step_from_gpu_state(s, p, prec, timed=True):
         _say(f"  gpu {t1 - t0:.2f} s, oracle {time.time() - t1:.1f} s, {o.n} particles, injected {o.counters()[0]}")
     if o_shift is not None:
         o_shift.step(1)
-    return o, o_shift
+    return o, o_shift, before
+
+
+def _momenta(o):
+    """Positions and momenta at the start of a step, by id."""
+    P = o.particles()
+    return {k: P[k] for k in ("id", "x", "y", "ur", "ut", "up")}
 
 
 def _sim(p, P, prec, capacity, ids=True):
@@ -165,12 +198,12 @@ def test_dipole_rotator_1024_full_size(prec):
     del P
     inj = 0
     for k in range(2):
-        o, o_shift = _step_from_gpu_state(s, p, prec)
+        o, o_shift, before = _step_from_gpu_state(s, p, prec)
         assert s.counts()["injected"] == o.counters()[0] + inj
         inj = s.counts()["injected"]
         _say(f" step {k} (sorts: {k == 0})")
-        _compare_step(o, s, p, prec, o_shift=o_shift)
-        del o, o_shift
+        _compare_step(o, s, p, prec, o_shift=o_shift, before=before)
+        del o, o_shift, before
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -189,12 +222,12 @@ def test_precision_stress_2048_window(prec):
     del P
     inj = 0
     for k in range(2):
-        o, o_shift = _step_from_gpu_state(s, p, prec)
+        o, o_shift, before = _step_from_gpu_state(s, p, prec)
         assert s.counts()["injected"] == o.counters()[0] + inj
         inj = s.counts()["injected"]
         _say(f" step {k}")
-        _compare_step(o, s, p, prec, particles=k == 1, o_shift=o_shift)
-        del o, o_shift
+        _compare_step(o, s, p, prec, particles=k == 1, o_shift=o_shift, before=before)
+        del o, o_shift, before
 
 
 def test_plain_fp64_64x64_100_steps():
@@ -211,11 +244,11 @@ def test_plain_fp64_64x64_100_steps():
         if k - done - 1 > 0:
             s.step(k - done - 1)
             o_run.step(k - done - 1)
-        o, o_shift = _step_from_gpu_state(s, p, "fp64", timed=False)
+        o, o_shift, before = _step_from_gpu_state(s, p, "fp64", timed=False)
         o_run.step(1)
         done = k
         _say(f"plain fp64, step {done}")
-        _compare_step(o, s, p, "fp64", o_shift=o_shift)
+        _compare_step(o, s, p, "fp64", o_shift=o_shift, before=before)
         rep = {}
         compare_fields(o_run, s, 1.0, report=rep)
         _say(f"  run alongside from step 0 (reported): worst field {max(rep.values()):.2e}")
@@ -232,9 +265,9 @@ def test_monopole_rotator_512_first_steps(prec):
     s = _sim(p, None, prec, 16 << 20)
     for k in range(3):
         s.step(9)
-        o, o_shift = _step_from_gpu_state(s, p, prec, timed=False)
+        o, o_shift, before = _step_from_gpu_state(s, p, prec, timed=False)
         _say(f"monopole rotator {prec} after {10 * (k + 1)} steps: {o.n} particles")
-        _compare_step(o, s, p, prec, o_shift=o_shift)
+        _compare_step(o, s, p, prec, o_shift=o_shift, before=before)
         assert np.all(np.abs(s.carry() - o.carry()) <= carry_atol(o, p, prec))
     assert o.n > 0
 
@@ -254,6 +287,44 @@ def test_smallest_ensemble_runs_as_one_batch():
         pairs = [(d, oracle_from_sim(s, d["params"]), s) for d, _, s in pairs]
         b.step(1)
         for d, o, s in pairs:
+            before = _momenta(o)
             o.step(1)
             _say(f"{d['name']} step {k}")
-            _compare_step(o, s, d["params"], "fp32")
+            _compare_step(o, s, d["params"], "fp32", before=before)
+
+
+def test_whole_ensemble_one_batched_step():
+    """All 64 runs of the ensemble (320M particles) in the benchmark's
+    launch configuration: 16 particles per thread, each run's sort tile and
+    interval picked by the autotuner over 4 steps, then the runs stepped
+    together as one batch.  After two batched steps, the next batched step
+    of every run against its own oracle loaded from that run's state."""
+    from collections import Counter
+
+    from paper_1407_1810_amd.binding import Batch, Sim
+    runs = W.config(4)["runs"]
+    sims, picks = [], Counter()
+    t0 = time.time()
+    for d in runs:
+        p = d["params"]
+        P = W.pair_plasma(p, d["pairs_per_cell"], d["theta_T"], d["weight"], d["seed"])
+        s = Sim(p, precision="fp32", capacity=2 * len(P["x"]) + (4 << 20), chunk_ppt=PPT)
+        s.add_particles(P["x"], P["y"], P["ur"], P["ut"], P["up"], P["w"], P["id"])
+        del P
+        best, _ = s.autotune(steps=4)
+        picks[f"{best[0]}x{best[1]}/K{best[2]}"] += 1
+        sims.append(s)
+    _say(f"ensemble: {len(sims)} runs, {sum(s.counts()['live'] for s in sims)} particles, loaded and autotuned "
+         f"in {time.time() - t0:.0f} s: {dict(picks)}")
+    b = Batch(sims)
+    b.step(2)
+    oracles = [oracle_from_sim(s, d["params"]) for d, s in zip(runs, sims)]
+    b.step(1)
+    for k, d in enumerate(runs):
+        o = oracles[k]
+        before = _momenta(o)
+        o.step(1)
+        _say(f"{d['name']}: {o.n} particles, injected {o.counters()[0]}")
+        _compare_step(o, sims[k], d["params"], "fp32", before=before)
+        oracles[k] = None
+    b.close()
