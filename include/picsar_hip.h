@@ -133,8 +133,9 @@ pic_status pic_init_grid(pic_ctx *ctx, const pic_grid_desc *grid, const pic_phys
  * signed macro charge w, all host FP64 arrays of length n); id may be NULL,
  * then ids are the storage slots in order of arrival.  Each particle is
  * stored as an int32 cell plus in-cell offsets (rounded once to FP32 in an
- * FP32 context).  PIC_EINVAL if a position lies outside the ranges above,
- * PIC_ECAPACITY if the store would overflow (nothing is then appended). */
+ * FP32 context).  PIC_EINVAL if a position lies outside the ranges above
+ * or a momentum or weight is not finite, PIC_ECAPACITY if the store would
+ * overflow (nothing is then appended in either case). */
 pic_status pic_inject_particles(pic_ctx *ctx, int64_t n, const double *x, const double *y,
                                 const double *ur, const double *ut, const double *up,
                                 const double *w, const uint64_t *id);

@@ -92,6 +92,14 @@ double *scratch_on(int device)
     return g_scratch[device];
 }
 
+// The address scratch_on recorded for `device`, or null before it ran there.
+double *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
+
 // Per-stage device time from HIP events recorded between the launches of
 // eagerly enqueued steps.
 enum { kStSort = 0, kStFaraday, kStPush, kStFilter, kStAmpere, kStAbsorb, kStInject, kStZero, kStTotal, kStages };
@@ -654,15 +662,19 @@ public:
     SortSched sched() { return SortSched{rd_.sort_interval, &sched_step_, &sched_need_}; }
 
     // Checks of an append of n particles from the host (positions inside the
-    // grid, room in the store); returns the first slot they take and the
-    // current buffer, and raises the largest |w| held.
-    unsigned long long inject_begin(int64_t n, const double *x, const double *y, const double *w, int &cur)
+    // grid, finite momenta and weights, room in the store); returns the first
+    // slot they take and the current buffer, and raises the largest |w| held
+    // (the deposit's fixed-point scale, which a non-finite weight would void).
+    unsigned long long inject_begin(int64_t n, const double *x, const double *y, const double *ur,
+                                    const double *ut, const double *up, const double *w, int &cur)
     {
         const int nr = gd.nr, nth = gd.nth;
         const double lim = gd.n_filt + 1.0;
         for (int64_t q = 0; q < n; ++q) {
             if (!(x[q] >= -lim && x[q] <= nr + lim && y[q] >= 0.0 && y[q] <= nth))
                 throw StatusError{PIC_EINVAL, "particle position outside the grid"};
+            if (!(std::isfinite(ur[q]) && std::isfinite(ut[q]) && std::isfinite(up[q]) && std::isfinite(w[q])))
+                throw StatusError{PIC_EINVAL, "non-finite particle momentum or weight"};
         }
         unsigned long long c[kNumCounters];
         read_counters(c);
@@ -704,7 +716,7 @@ public:
     {
         if (n == 0) return;
         int cur = 0;
-        const unsigned long long ntot = inject_begin(n, x, y, w, cur);
+        const unsigned long long ntot = inject_begin(n, x, y, ur, ut, up, w, cur);
         const int64_t chunk = 1 << 22;
         double *stage = dev_alloc<double>(6 * (size_t)std::min(n, chunk));
         uint64_t *sid = id ? dev_alloc<uint64_t>((size_t)std::min(n, chunk)) : nullptr;
@@ -740,7 +752,7 @@ public:
     {
         if (n == 0) return;
         int cur = 0;
-        const unsigned long long ntot = inject_begin(n, x, y, w, cur);
+        const unsigned long long ntot = inject_begin(n, x, y, ur, ut, up, w, cur);
         const double *srcs[6] = {x, y, ur, ut, up, w};
         for (int a = 0; a < 6; ++a)
             HIPCHK(hipMemcpyAsync(scratch + (size_t)a * n, srcs[a], sizeof(double) * n, hipMemcpyHostToDevice,
@@ -1624,7 +1636,7 @@ pic_status pic_inject_particles_noalloc(pic_ctx *ctx, int64_t n, const double *x
         if (n > kNoAllocMaxParticles)
             throw StatusError{PIC_EINVAL, "pic_inject_particles_noalloc takes at most " +
                                               std::to_string(kNoAllocMaxParticles) + " particles per call"};
-        double *sp = g_scratch[ctx->device];
+        double *sp = scratch_of(ctx->device);
         if (!sp) throw StatusError{PIC_ESTATE, "no staging memory on this device (pic_init has not run on it)"};
         ctx->eng->inject_noalloc(n, x, y, ur, ut, up, w, id, sp);
     });

@@ -330,6 +330,13 @@ def test_error_codes():
     with pytest.raises(PicError) as e:
         s.add_particles([3.5], [-0.5], [0.0], [0.0], [0.0], [1.0])
     assert e.value.code == -1
+    # a non-finite weight (it would void the deposit's fixed-point scale) or
+    # momentum: refused, nothing appended
+    for bad in ([3.5], [2.5], [0.0], [0.0], [0.0], [math.inf]), ([3.5], [2.5], [math.nan], [0.0], [0.0], [1.0]):
+        with pytest.raises(PicError) as e:
+            s.add_particles(*bad)
+        assert e.value.code == -1 and "non-finite" in str(e.value)
+    assert s.counts()["live"] == 0
     # CFL: a particle moving more than a cell per step (c > 1 cell per step)
     q = dict(p, c=3.0)
     s2 = Sim(q, precision="fp64", capacity=10)
