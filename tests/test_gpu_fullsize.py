@@ -45,8 +45,8 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import (TOL, carry_atol, compare_fields, momentum_scale, oracle_from_sim, oracles_from_sim,
-                         shifted_floor, widen_by_update_terms)
+from parity_util import (OWN_TOL_FP32, TOL, carry_atol, compare_fields, coordinate_gates, momentum_scale,
+                         oracle_from_sim, oracles_from_sim, shifted_floor, widen_by_update_terms)
 
 pytestmark = pytest.mark.gpu
 
@@ -109,7 +109,8 @@ def _compare_large(o, s, tol, nth, band, before=None):
     ig, jg = np.floor(Ps["x"]), np.minimum(np.floor(Ps["y"]), nth - 1)
     dx = np.abs(Po["x"] - np.round(Po["x"]))
     dy = np.abs(Po["y"] - np.round(Po["y"]))
-    bad = ((io != ig) & (dx > band)) | ((jo != jg) & (dy > band))
+    gx, gy, bx, by = coordinate_gates(o, tol["off"], band)
+    bad = ((io != ig) & (dx > bx)) | ((jo != jg) & (dy > by))
     in_band = int(((io != ig) | (jo != jg)).sum() - bad.sum())
     assert not bad.any(), f"{int(bad.sum())} cell mismatches outside the band"
     same = (io == ig) & (jo == jg)
@@ -131,14 +132,11 @@ def _compare_large(o, s, tol, nth, band, before=None):
             _say(f"  worst particle id {int(Po['id'][q])}: oracle u ({Po['ur'][q]:.6e}, {Po['ut'][q]:.6e}, "
                  f"{Po['up'][q]:.6e}), gpu u ({Ps['ur'][q]:.6e}, {Ps['ut'][q]:.6e}, {Ps['up'][q]:.6e}), "
                  f"momentum scale {umag[q]:.3e}")
-    assert ex <= tol["off"] and ey <= tol["off"]
+    assert ex <= gx and ey <= gy, (ex, ey, gx, gy)
     assert emom <= tol["mom"]
     assert np.abs(Po["w"] - Ps["w"]).max() <= 1e-7 * np.abs(Po["w"]).max()
 
 
-# FP32: error against a component's own inf-norm (components at least 1e-2
-# of their vector's scale)
-OWN_TOL_FP32 = 1e-4
 
 
 def _compare_step(o, s, p, prec, particles=True, o_shift=None, before=None):

@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 from paper_1407_1810_amd import workloads as W
-from parity_util import (FIELD_COMPS, TOL, carry_atol, compare_fields, compare_particles, make_pair,
-                         oracle_from_sim, random_fields, round_to_storage)
+from parity_util import (FIELD_COMPS, OWN_TOL_FP32, TOL, carry_atol, compare_fields, compare_particles, make_pair,
+                         oracle_from_sim, oracles_from_sim, random_fields, round_to_storage, shifted_floor)
 
 pytestmark = pytest.mark.gpu
 
@@ -315,6 +315,51 @@ def test_edge_cases_poles_conductors_deletion():
             assert s.counts()["deleted"] - d0 == o.counters()[1]
             deleted += o.counters()[1]
         assert deleted >= 1  # something was deleted
+
+
+@pytest.mark.parametrize("prec,nr,nth,r_ratio", [("fp64", 64, 8191, math.exp(128 / 8191)),
+                                                 ("fp32", 64, 8191, math.exp(128 / 8191)),
+                                                 ("fp64", 16000, 4, 6.0)])
+def test_largest_grids(prec, nr, nth, r_ratio):
+    """The grid extremes the library accepts: 8191 meridional cells (eight
+    injection nodes per thread, the longest rows of filter strips and
+    tiles, an odd count) on a thin shell whose cells are as wide as they are
+    long at the equator, and 16000 radial cells on the fewest meridional
+    ones (in FP64 only: its cells are thousands of times wider in theta
+    than in r, so a step moves a particle some 3e-5 of a cell meridionally,
+    which an FP32 offset (spacing 6e-8 near one half) resolves to about
+    2e-3, and the meridional face charge with it: outside the FP32
+    tolerance, measured 2e-5 of E's scale and 3e-4 of E_theta's own); a
+    rotating dipole with injection (the carry of every
+    node drawn in [0, 1), as in a running simulation), unpaired particles,
+    two steps, each from identical input bits (the first sorts).  At 8191
+    meridional cells a unit in the last place of the oracle's absolute
+    coordinate is 9e-13 cells, so the FP64 gate is widened to four times the
+    response of an oracle loaded with shifted coordinates (shifted_floor),
+    as at the benchmark sizes; FP32 fields are gated as there too, against
+    their vector field's scale (and at OWN_TOL_FP32 against their own for
+    components at least 1e-2 of it)."""
+    cfg, P = _small(nr=nr, nth=nth, pairs_per_cell=2, n_filt=3, absorb_cells=4, theta_T=0.3, inject=1,
+                    omega_frac=0.3, bg="dipole", r_ratio=r_ratio)
+    p = cfg["params"]
+    P["x"][1::4] = np.clip(P["x"][1::4] + 0.37, 0.0, p["nr"] - 1e-9)
+    _say("largest grids", prec, nr, nth, len(P["x"]))
+    _, s = make_pair(p, P, prec, carry=np.random.default_rng(5).uniform(0.0, 1.0, nth + 1))
+    t = TOL[prec]
+    injected = 0
+    for k in range(2):
+        o, *rest = oracles_from_sim(s, p, (False, True) if prec == "fp64" else (False,))
+        before = s.particles()
+        o.step(1)
+        s.step(1)
+        for q in rest:
+            q.step(1)
+        injected += o.counters()[0]
+        compare_fields(o, s, t["field"], vector_scale=prec == "fp32", own_tol=OWN_TOL_FP32 if prec == "fp32" else None,
+                       floor=shifted_floor(o, rest[0]) if rest else None)
+        compare_particles(o, s, t, p["nth"], t["band"], before=before)
+        assert np.all(np.abs(s.carry() - o.carry()) <= carry_atol(o, p, prec))
+    assert s.counts()["injected"] == injected > 0
 
 
 def test_error_codes():
