@@ -82,12 +82,12 @@ enum { PIC_FLAG_IDS = 1 };                        /* carry a uint64 id per parti
  * counting-sort tile and how often particles are re-sorted (0 = default);
  * they change speed, never results beyond float reordering. */
 typedef struct {
-    int32_t nr, nth;          /* cells; nth >= 4 */
+    int32_t nr, nth;          /* cells; 2 <= nr <= 16000, 4 <= nth <= 8191 */
     double r_in, r_out;       /* conductor radii, 0 < r_in < r_out */
     int32_t r_kind, th_kind;  /* PIC_R_*, PIC_TH_* */
     double c;                 /* light speed, length units per step */
     int32_t n_filt;           /* 1-2-1 filter passes, 0..8 (App. B) */
-    int32_t absorb_cells;     /* lossy layer width in cells, 0 = off (Sec. 3.4.1) */
+    int32_t absorb_cells;     /* lossy layer width in cells, 0 = off, at most nr (Sec. 3.4.1) */
     double sigma_max;         /* sigma* at the outer conductor, eq. (EBcond) */
     int32_t precision;        /* PIC_FP64 | PIC_FP32 */
     int32_t mover;            /* PIC_VAY | PIC_BORIS */
