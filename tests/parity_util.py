@@ -143,16 +143,49 @@ def compare_fields(o, s, tol, comps=FIELD_COMPS + ["Fr", "Fth", "Fph"], report=N
     return worst
 
 
+def positions_by_id(b_ids, ids) -> np.ndarray:
+    """Index in b_ids of each of ids, -1 where absent.  Ids below 2^63
+    (particles loaded from the host, numbered densely from 0) are looked up
+    in a table indexed by id; the others (injected pairs, few) by sorting,
+    so that a step of 2e8 particles is matched in seconds."""
+    b_ids = np.asarray(b_ids, dtype=np.uint64)
+    ids = np.asarray(ids, dtype=np.uint64)
+    out = np.full(len(ids), -1, dtype=np.int64)
+    top = np.uint64(1 << 63)
+    bpre, ipre = b_ids < top, ids < top
+    idx_pre = np.nonzero(bpre)[0]
+    if len(idx_pre) and ipre.any():
+        bp = b_ids[idx_pre].astype(np.int64)
+        n = int(bp.max()) + 1
+        q = ids[ipre].astype(np.int64)
+        if n <= 4 * len(bp) + (1 << 20):
+            table = np.full(n, -1, dtype=np.int64)
+            table[bp] = idx_pre
+            inside = q < n
+            pos = np.full(len(q), -1, dtype=np.int64)
+            pos[inside] = table[q[inside]]
+            out[ipre] = pos
+        else:
+            out[ipre] = _positions_sorted(b_ids[idx_pre], idx_pre, ids[ipre])
+    idx_inj = np.nonzero(~bpre)[0]
+    if len(idx_inj) and (~ipre).any():
+        out[~ipre] = _positions_sorted(b_ids[idx_inj], idx_inj, ids[~ipre])
+    return out
+
+
+def _positions_sorted(keys, where, q):
+    order = np.argsort(keys, kind="stable")
+    ks = keys[order]
+    k = np.clip(np.searchsorted(ks, q), 0, len(ks) - 1)
+    return np.where(ks[k] == q, where[order][k], -1)
+
+
 def momentum_scale(before, ids):
     """|u| before the step of the particles with the given ids (0 for those
     not in `before`: injected during the step), from a particles() dict."""
-    b_ids = np.asarray(before["id"])
-    order = np.argsort(b_ids)
-    b_sorted = b_ids[order]
-    mag = np.sqrt(before["ur"] ** 2 + before["ut"] ** 2 + before["up"] ** 2)[order]
-    k = np.clip(np.searchsorted(b_sorted, ids), 0, max(len(b_sorted) - 1, 0))
-    hit = (b_sorted[k] == ids) if len(b_sorted) else np.zeros(len(ids), bool)
-    return np.where(hit, mag[k] if len(b_sorted) else 0.0, 0.0)
+    pos = positions_by_id(before["id"], ids)
+    mag = np.sqrt(before["ur"] ** 2 + before["ut"] ** 2 + before["up"] ** 2)
+    return np.where(pos >= 0, mag[np.maximum(pos, 0)] if len(mag) else 0.0, 0.0)
 
 
 def update_term_scale(o: Oracle, before: dict, ids) -> np.ndarray:
@@ -168,9 +201,7 @@ def update_term_scale(o: Oracle, before: dict, ids) -> np.ndarray:
     zero inside the inner conductor; beyond the outer conductor particles
     fly without force."""
     eps = abs(o.params.get("q_over_m", 1.0)) / (2.0 * o.params["c"])
-    b_ids = np.asarray(before["id"])
-    order = np.argsort(b_ids)
-    k = order[np.searchsorted(b_ids[order], ids)]
+    k = positions_by_id(before["id"], ids)
     t = float(o.step_index - 1)
     out = np.zeros(len(ids))
     for q, m in enumerate(k):
@@ -193,10 +224,9 @@ def widen_by_update_terms(o: Oracle, before: dict, ids, umag, du, tol: float, li
     their error.  Returns the new scale and how many particles it raised."""
     rel = du / (umag + 1e-3)
     cand = np.nonzero(rel > tol)[0]
-    if len(cand) == 0 or len(cand) > limit or "x" not in before:
+    if len(cand) == 0 or len(cand) > limit or "x" not in before or not hasattr(o, "gather"):
         return umag, 0
-    in_before = np.isin(ids[cand], np.asarray(before["id"]))
-    cand = cand[in_before]
+    cand = cand[positions_by_id(before["id"], ids[cand]) >= 0]
     umag = umag.copy()
     term = update_term_scale(o, before, ids[cand])
     raised = int((term > umag[cand]).sum())
@@ -219,8 +249,11 @@ def coordinate_gates(o, off: float, band: float):
     9.1e-13 cells of y at 8191 meridional cells and 9.1e-13 cells of x at the
     1024-cell dipole rotator (radii up to 4945 units, the first cell one
     unit wide).  On the small grids of the parity tests (radii below 300
-    units) the gates stay off and band."""
-    p = o.params
+    units) the gates stay off and band, as they do when o is a second GPU
+    context (no oracle: the two sides share the representation)."""
+    p = getattr(o, "params", None)
+    if p is None or not hasattr(o, "g"):
+        return off, off, band, band
     if p.get("r_kind", "log") == "log":
         dr_min = p["r_in"] * math.expm1(math.log(p["r_out"] / p["r_in"]) / p["nr"])
     else:
